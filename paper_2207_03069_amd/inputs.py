@@ -1,0 +1,150 @@
+"""Seeded synthetic inputs for the bulk-search workloads.
+
+This module only draws problems and bit vectors; it holds none of the search
+arithmetic and is shared by the tests, the benchmark and the oracle checks.
+Every generator uses ``numpy.random.default_rng(seed)`` with the draw order
+stated in its docstring.  Bit vectors are numpy uint8 arrays of 0/1.
+
+Workload shapes follow the paper's problem families (Section II and VI):
+dense random QUBOs, max-cut graphs mapped to QUBO (Section II-A) and TSP as a
+one-hot QUBO (the circular-flow special case of Section II-B).  The benchmark
+instances of the paper (K2000, G-set, QAPLIB, the D-Wave QASP graph) are not
+available; these generators stand in for them with the same shapes.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def dense_qubo(n: int, lo: int, hi: int, seed: int, dtype=np.int16) -> np.ndarray:
+    """Symmetric W: the upper triangle including the diagonal is drawn uniform
+    in [lo, hi] (one n x n draw, row-major, upper part kept) and mirrored."""
+    rng = np.random.default_rng(seed)
+    U = rng.integers(lo, hi + 1, size=(n, n), dtype=np.int64)
+    W = np.triu(U)
+    W = W + np.triu(W, 1).T
+    return W.astype(dtype)
+
+
+def maxcut_graph(n: int, p: float, seed: int):
+    """Erdos-Renyi G(n, p) with +-1 edge weights of equal probability.
+    Draw order: an n x n uniform matrix (edge i<j present iff U_ij < p), then
+    an n x n sign matrix (weight of edge i<j is +1 iff S_ij = 1).
+    Returns (edges int64 [m,2] with i<j, weights int64 [m])."""
+    rng = np.random.default_rng(seed)
+    U = rng.random((n, n))
+    S = rng.integers(0, 2, size=(n, n))
+    iu, ju = np.triu_indices(n, 1)
+    keep = U[iu, ju] < p
+    edges = np.stack([iu[keep], ju[keep]], axis=1).astype(np.int64)
+    w = np.where(S[iu[keep], ju[keep]] == 1, 1, -1).astype(np.int64)
+    return edges, w
+
+
+def maxcut_qubo(n: int, edges: np.ndarray, w: np.ndarray, dtype=np.int16) -> np.ndarray:
+    """Section II-A: each edge contributes w (2 x_i x_j - x_i^2 - x_j^2).  With
+    the energy summed over all ordered pairs this is W_ij = W_ji = w_ij and
+    W_ii = -sum_j w_ij, so E(X) = -cut(X)."""
+    W = np.zeros((n, n), dtype=np.int64)
+    W[edges[:, 0], edges[:, 1]] = w
+    W[edges[:, 1], edges[:, 0]] = w
+    np.fill_diagonal(W, -W.sum(axis=1))
+    return W.astype(dtype)
+
+
+def maxcut_instance(n: int = 800, p: float = 0.06, seed: int = 0, dtype=np.int16):
+    edges, w = maxcut_graph(n, p, seed)
+    return maxcut_qubo(n, edges, w, dtype), edges, w
+
+
+def rounded_distance(dx: int, dy: int) -> int:
+    """round(sqrt(dx^2 + dy^2)) in exact integer arithmetic (half rounds up)."""
+    s = dx * dx + dy * dy
+    r = math.isqrt(s)
+    return r + (1 if s > r * r + r else 0)
+
+
+def tsp_cities(ncity: int = 32, grid: int = 1000, seed: int = 0):
+    """City coordinates uniform integers in [0, grid-1]^2; returns (xy, D)."""
+    rng = np.random.default_rng(seed)
+    xy = rng.integers(0, grid, size=(ncity, 2), dtype=np.int64)
+    D = np.zeros((ncity, ncity), dtype=np.int64)
+    for a in range(ncity):
+        for b in range(ncity):
+            D[a, b] = rounded_distance(int(xy[a, 0] - xy[b, 0]), int(xy[a, 1] - xy[b, 1]))
+    return xy, D
+
+
+def tsp_qubo(D: np.ndarray, A: int | None = None, dtype=np.int32) -> np.ndarray:
+    """TSP as a one-hot QUBO, bit (c, t) = city c at tour position t at index
+    c * N + t (the indexing of Section II-B).  W_aa = -2A; W_ab = A when a, b
+    share exactly one of {city, position}; W_ab = d(c, c') when c != c' and
+    t' = t +- 1 (mod N); else 0.  A feasible tour of length L has
+    E = 2 L - 2 N A.  Default A = 2 max d."""
+    N = D.shape[0]
+    if A is None:
+        A = 2 * int(D.max())
+    n = N * N
+    W = np.zeros((n, n), dtype=np.int64)
+    for c in range(N):
+        for t in range(N):
+            a = c * N + t
+            for c2 in range(N):
+                for t2 in range(N):
+                    b = c2 * N + t2
+                    if a == b:
+                        W[a, b] = -2 * A
+                    elif (c == c2) != (t == t2):
+                        W[a, b] = A
+                    elif c != c2 and ((t2 - t) % N in (1, N - 1)):
+                        W[a, b] = D[c, c2]
+    return W.astype(dtype)
+
+
+def tsp_instance(ncity: int = 32, seed: int = 0):
+    xy, D = tsp_cities(ncity, seed=seed)
+    A = 2 * int(D.max())
+    return tsp_qubo(D, A), D, A
+
+
+def batched_sizes(count: int = 256, lo: int = 256, ratio: int = 16, seed: int = 0) -> np.ndarray:
+    """Problem sizes n = floor(lo * ratio^U), U ~ U[0,1), for the many-problem
+    workload (log-uniform in [256, 4096))."""
+    rng = np.random.default_rng(seed)
+    U = rng.random(count)
+    return np.floor(lo * np.power(float(ratio), U)).astype(np.int64)
+
+
+def batched_problems(count: int = 256, seed: int = 0, lo: int = -1000, hi: int = 1000):
+    """Sizes from batched_sizes(seed), then problem p drawn by
+    dense_qubo(n_p, lo, hi, seed * 100003 + p + 1)."""
+    sizes = batched_sizes(count, seed=seed)
+    return [dense_qubo(int(n), lo, hi, seed * 100003 + p + 1) for p, n in enumerate(sizes)]
+
+
+def random_bits(count: int, n: int, seed: int) -> np.ndarray:
+    """[count, n] uint8 uniform 0/1."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2, size=(count, n), dtype=np.uint8)
+
+
+def pack_bits(bits: np.ndarray) -> np.ndarray:
+    """[..., n] 0/1 -> [..., ceil(n/64)] uint64, bit k in word k//64 at k%64."""
+    bits = np.asarray(bits, dtype=np.uint8)
+    n = bits.shape[-1]
+    words = (n + 63) // 64
+    pad = np.zeros(bits.shape[:-1] + (words * 64,), dtype=np.uint8)
+    pad[..., :n] = bits
+    by = np.packbits(pad.reshape(bits.shape[:-1] + (words * 8, 8)), axis=-1, bitorder="little")
+    return np.ascontiguousarray(by.reshape(bits.shape[:-1] + (words * 8,))).view(np.uint64)
+
+
+def unpack_bits(words: np.ndarray, n: int) -> np.ndarray:
+    """Inverse of pack_bits."""
+    words = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+    by = words.view(np.uint8)
+    bits = np.unpackbits(by.reshape(words.shape[:-1] + (words.shape[-1] * 8, 1)), axis=-1,
+                         bitorder="little")
+    return bits.reshape(words.shape[:-1] + (words.shape[-1] * 64,))[..., :n].copy()
