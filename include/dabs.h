@@ -1,0 +1,232 @@
+/*
+ * dabs.h -- C-ABI of the MI355X bulk-search library (libdabs.so).
+ *
+ * The library implements the data-parallel hot path of Diverse Adaptive Bulk
+ * Search (Nakano et al., arXiv 2207.03069): many independent search instances
+ * over one QUBO matrix W, each keeping a bit vector X, its energy E(X) and the
+ * flip deltas, choosing a bit by a search rule, flipping it and updating every
+ * delta from one row of W; plus the batch search, packets and the genetic
+ * algorithm on device-resident solution pools.
+ *
+ * Conventions shared by every call
+ *  - Energy: E(X) = sum_i sum_j W_ij x_i x_j over all ordered pairs (Section
+ *    II, Eq. (2)); W must be symmetric.  Energies are int64.
+ *  - Bit vectors: packed little-endian uint64 words, bit k of a vector is bit
+ *    (k mod 64) of word k/64; a vector of n bits occupies nwords(n) =
+ *    ceil(n/64) words; padding bits must be zero on input and are zero on
+ *    output.  Arrays of vectors are [count][nwords(n)] row-major.
+ *  - Memory: every pointer argument named *_dev is device memory owned by the
+ *    caller (for instance a torch tensor's data pointer); the library never
+ *    frees or retains it after the call's stream work completes.  Handles
+ *    (dabs_problem, dabs_solver) are library-owned and freed by their
+ *    destroy call.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls that take a stream enqueue their work on it and return
+ *    without waiting, unless stated otherwise.
+ *  - Errors: every call returns a dabs_status; nothing throws or aborts across
+ *    the ABI.  dabs_last_error() returns a thread-local message for the last
+ *    failing call of the calling thread.
+ */
+#ifndef DABS_H
+#define DABS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DABS_OK = 0,
+    DABS_E_INVALID = -1,        /* bad argument (null pointer, size, rule, ...) */
+    DABS_E_NOT_SYMMETRIC = -2,  /* W_ij != W_ji for some i, j */
+    DABS_E_RANGE = -3,          /* W too large for the exact device representation */
+    DABS_E_NOMEM = -4,          /* device allocation failed */
+    DABS_E_HIP = -5,            /* a HIP runtime call failed */
+    DABS_E_UNSUPPORTED = -6     /* n outside the sizes this build supports */
+} dabs_status;
+
+typedef enum { DABS_W_I16 = 0, DABS_W_I32 = 1 } dabs_wtype;
+
+/* Search rules: Section III-A (Greedy, Straight, MaxMin, CyclicMin,
+ * RandomMin, PositiveMin, TwoNeighbor) and tabu greedy (T iterations, each
+ * flipping the non-tabu argmin delta). */
+typedef enum {
+    DABS_GREEDY = 0, DABS_STRAIGHT = 1, DABS_MAXMIN = 2, DABS_CYCLICMIN = 3,
+    DABS_RANDOMMIN = 4, DABS_POSITIVEMIN = 5, DABS_TWONEIGHBOR = 6, DABS_TABU_GREEDY = 7
+} dabs_rule;
+
+/* Genetic operations: Section IV-A (Random, Best, Mutation, Crossover, Zero,
+ * One, IntervalZero) and IV-B (Xrossover). */
+typedef enum {
+    DABS_OP_RANDOM = 0, DABS_OP_BEST = 1, DABS_OP_MUTATION = 2, DABS_OP_CROSSOVER = 3,
+    DABS_OP_XROSSOVER = 4, DABS_OP_ZERO = 5, DABS_OP_ONE = 6, DABS_OP_INTERVALZERO = 7
+} dabs_op;
+
+typedef struct dabs_problem dabs_problem;
+typedef struct dabs_solver dabs_solver;
+
+/* Static text for a status code. */
+const char *dabs_strerror(int status);
+/* Message of the calling thread's last failing call ("" if none). */
+const char *dabs_last_error(void);
+/* Largest n this build supports for a weight type. */
+int32_t dabs_max_n(int32_t wtype);
+
+/*
+ * Load a QUBO matrix (the W of Section II, Eq. (2)).
+ *   w_dev  device pointer to an n x n row-major matrix of int16 (wtype
+ *          DABS_W_I16) or int32 (DABS_W_I32) with row stride ld >= n elements.
+ * The library validates W on the device (symmetry; delta bound
+ * B = max_k |W_kk| + 2 sum_{j!=k} |W_kj| < 2^23 - 1, which keeps every delta and
+ * local field exact in the device representation), then copies it into its
+ * own padded layout.  This call synchronises `stream` once (validation
+ * result); the caller may free w_dev afterwards.
+ * Errors: DABS_E_INVALID (null, n < 1, ld < n, bad wtype), DABS_E_UNSUPPORTED
+ * (n > dabs_max_n), DABS_E_NOT_SYMMETRIC, DABS_E_RANGE (B >= 2^23 - 1),
+ * DABS_E_NOMEM, DABS_E_HIP.  *out is set only on success.
+ */
+int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
+                        void *stream, dabs_problem **out);
+int dabs_problem_destroy(dabs_problem *p);
+/* n, weight type and delta bound B of a loaded problem (any pointer may be NULL). */
+int dabs_problem_info(const dabs_problem *p, int32_t *n, int32_t *wtype, int64_t *bound);
+
+/*
+ * Energies of `count` vectors (Eq. (2)) computed from scratch.
+ *   x_dev [count][nwords] packed vectors; e_dev [count] int64 output.
+ */
+int dabs_energy(const dabs_problem *p, const uint64_t *x_dev, int32_t count, int64_t *e_dev,
+                void *stream);
+
+/* Parameters of one search call (one phase of one rule per instance). */
+typedef struct {
+    int32_t rule;        /* dabs_rule */
+    int32_t T;           /* iterations for MaxMin, CyclicMin, RandomMin, PositiveMin,
+                            tabu greedy; ignored by Straight and TwoNeighbor */
+    int32_t tau;         /* tabu tenure (0 = no tabu) */
+    int32_t greedy_cap;  /* upper bound on the flips of one Greedy phase (<= 0: 64 n) */
+    uint64_t seed;       /* key of the counter-based generator */
+    uint32_t phase;      /* phase counter word of the generator's counter */
+    uint32_t inst0;      /* instance id of the first vector (generator counter word) */
+} dabs_search_params;
+
+/*
+ * One search call (Section III-A, Steps 1-4) for `count` independent
+ * instances.  Instance c starts at x_dev[c] (BEST := X), runs one phase of
+ * params->rule, and writes:
+ *   x_dev[c]        final X (in/out)
+ *   best_dev[c]     BEST, the best vector seen by Step 1 at every visited state
+ *   best_e_dev[c]   E(BEST)
+ *   e_dev[c]        E(final X)
+ *   delta_dev       nullable; [count][n] int32 final deltas
+ *   trace_dev       nullable; [count][trace_cap] int32 flipped bit per flip,
+ *                   -1 after the last flip
+ *   flips_dev       nullable; [count] int32 flips made
+ *   target_dev      [count][nwords] target vectors, required by DABS_STRAIGHT,
+ *                   ignored otherwise.
+ * Instance c uses generator counter words (iteration, inst0 + c, phase, tag).
+ */
+int dabs_search(const dabs_problem *p, const dabs_search_params *params, int32_t count,
+                uint64_t *x_dev, const uint64_t *target_dev, uint64_t *best_dev,
+                int64_t *best_e_dev, int64_t *e_dev, int32_t *delta_dev, int32_t *trace_dev,
+                int32_t trace_cap, int32_t *flips_dev, void *stream);
+
+/* Parameters of a batch search (Section III-B). */
+typedef struct {
+    int32_t T;           /* main-search flips, round(s n) */
+    int32_t Bn;          /* batch flips, round(b n) */
+    int32_t tau;         /* tabu tenure of the main searches */
+    int32_t greedy_cap;  /* as in dabs_search_params */
+    uint64_t seed;
+    uint32_t inst0;
+    uint32_t reserved;
+} dabs_batch_params;
+
+/*
+ * Batch search for `count` instances (Section III-B): BEST := X, Straight to
+ * target_dev[c], Greedy, then {main search algo_dev[c] (T flips; TwoNeighbor
+ * 2n-1 flips, once), Greedy} while the flips of this batch search are below
+ * Bn.  Packets (Section III-C): the target goes in, BEST and E(BEST) come
+ * out; the algorithm field is read only.
+ *   x_dev      [count][nwords] in/out current X (kept between batch searches)
+ *   target_dev [count][nwords] targets D
+ *   algo_dev   [count] int32 main rule (MaxMin .. TwoNeighbor)
+ *   phase_dev  [count] uint32 in/out main-phase counters (one per main phase)
+ *   best_dev, best_e_dev, e_dev  as in dabs_search
+ *   flips_dev  nullable [count] int32 flips of this batch search
+ */
+int dabs_batch_search(const dabs_problem *p, const dabs_batch_params *params, int32_t count,
+                      uint64_t *x_dev, const uint64_t *target_dev, const int32_t *algo_dev,
+                      uint32_t *phase_dev, uint64_t *best_dev, int64_t *best_e_dev,
+                      int64_t *e_dev, int32_t *flips_dev, void *stream);
+
+/* Parameters of the genetic algorithm on device pools (Section IV). */
+typedef struct {
+    int32_t n_algos;
+    int32_t algos[8];        /* enabled main algorithms (dabs_rule values) */
+    int32_t n_ops;
+    int32_t ops[16];         /* enabled genetic operations (dabs_op values) */
+    uint32_t p_explore;      /* u32 threshold of the uniform op/algo choice (5% = 214748365) */
+    uint32_t p_mutation;     /* per-bit u32 thresholds (1/8 = 536870912) */
+    uint32_t p_zero;
+    uint32_t p_one;
+    int32_t crossover_kind;  /* 0 uniform, 1 two-point */
+    int32_t capacity;        /* pool capacity m (1..1024) */
+    int32_t npools;          /* pools in the ring (instance i belongs to pool i mod npools) */
+    int32_t tau;
+    int32_t T;
+    int32_t Bn;
+    int32_t greedy_cap;
+    int32_t reserved;
+    uint64_t seed;
+} dabs_ga_params;
+
+/*
+ * Solver: `instances` search instances and `npools` solution pools on one
+ * problem, all device resident.  Instances start at X = 0; pools start full
+ * of random vectors with energy +inf (INT64_MAX) and random algorithm /
+ * operation columns.  Allocates its state on the device; the problem must
+ * outlive the solver.
+ */
+int dabs_solver_create(const dabs_problem *p, const dabs_ga_params *params, int32_t instances,
+                       void *stream, dabs_solver **out);
+int dabs_solver_destroy(dabs_solver *s);
+
+/*
+ * Run `rounds` generational rounds (Section IV with the batch search of
+ * Section III-B): every instance draws a target from its pool (adaptive
+ * op/algorithm choice, rank selection, genetic operation), runs one batch
+ * search, and the packets are inserted into the pools in instance order.
+ * If target_e is not NULL, the device records the first time (in ticks of
+ * the 100 MHz device clock, counted from the start of this call's first
+ * round) at which some instance's E(BEST) <= *target_e.
+ */
+int dabs_solver_run(dabs_solver *s, int32_t rounds, const int64_t *target_e, void *stream);
+
+/*
+ * Copy the pools out (device to device, on `stream`): bits [npools][capacity]
+ * [nwords], energies [npools][capacity] int64, algorithm and op columns
+ * [npools][capacity] int32.  Any pointer may be NULL.
+ */
+int dabs_solver_pools(const dabs_solver *s, uint64_t *bits_dev, int64_t *e_dev, int32_t *algo_dev,
+                      int32_t *op_dev, void *stream);
+
+/*
+ * Copy per-instance state out: current X [instances][nwords], E(X)
+ * [instances], main-phase counters [instances], and the total flips of all
+ * rounds so far (int64, one value).  Any pointer may be NULL.
+ */
+int dabs_solver_state(const dabs_solver *s, uint64_t *x_dev, int64_t *e_dev, uint32_t *phase_dev,
+                      int64_t *total_flips_dev, void *stream);
+
+/*
+ * Time-to-target record (ticks of the 100 MHz device clock since the start of
+ * the run that set it; -1 if not reached) and the best energy found so far, as
+ * two int64 values written to out_dev.
+ */
+int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,217 @@
+"""Python binding of libdabs.so, the MI355X bulk-search library.
+
+Argument marshalling only: every function here has the name of a C-ABI call
+in ``include/dabs.h``, takes torch tensors (device memory) and forwards their
+data pointers and the current HIP stream.  All work runs in the library's HIP
+kernels; there is no fallback path.  If ``libdabs.so`` has not been built the
+first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdabs.so")
+
+DABS_OK, DABS_E_INVALID, DABS_E_NOT_SYMMETRIC, DABS_E_RANGE, DABS_E_NOMEM, DABS_E_HIP, DABS_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+DABS_W_I16, DABS_W_I32 = 0, 1
+(DABS_GREEDY, DABS_STRAIGHT, DABS_MAXMIN, DABS_CYCLICMIN, DABS_RANDOMMIN, DABS_POSITIVEMIN,
+ DABS_TWONEIGHBOR, DABS_TABU_GREEDY) = range(8)
+(DABS_OP_RANDOM, DABS_OP_BEST, DABS_OP_MUTATION, DABS_OP_CROSSOVER, DABS_OP_XROSSOVER, DABS_OP_ZERO,
+ DABS_OP_ONE, DABS_OP_INTERVALZERO) = range(8)
+MAIN_ALGOS = (DABS_MAXMIN, DABS_CYCLICMIN, DABS_RANDOMMIN, DABS_POSITIVEMIN, DABS_TWONEIGHBOR)
+
+
+class DabsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+class dabs_search_params(C.Structure):
+    _fields_ = [("rule", C.c_int32), ("T", C.c_int32), ("tau", C.c_int32), ("greedy_cap", C.c_int32),
+                ("seed", C.c_uint64), ("phase", C.c_uint32), ("inst0", C.c_uint32)]
+
+
+class dabs_batch_params(C.Structure):
+    _fields_ = [("T", C.c_int32), ("Bn", C.c_int32), ("tau", C.c_int32), ("greedy_cap", C.c_int32),
+                ("seed", C.c_uint64), ("inst0", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class dabs_ga_params(C.Structure):
+    _fields_ = [("n_algos", C.c_int32), ("algos", C.c_int32 * 8), ("n_ops", C.c_int32), ("ops", C.c_int32 * 16),
+                ("p_explore", C.c_uint32), ("p_mutation", C.c_uint32), ("p_zero", C.c_uint32),
+                ("p_one", C.c_uint32), ("crossover_kind", C.c_int32), ("capacity", C.c_int32),
+                ("npools", C.c_int32), ("tau", C.c_int32), ("T", C.c_int32), ("Bn", C.c_int32),
+                ("greedy_cap", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+# every function the header declares: name -> (argtypes, restype)
+_P = C.c_void_p
+_SIGS = {
+    "dabs_strerror": ([C.c_int], C.c_char_p),
+    "dabs_last_error": ([], C.c_char_p),
+    "dabs_max_n": ([C.c_int32], C.c_int32),
+    "dabs_problem_create": ([_P, C.c_int32, C.c_int64, C.c_int32, _P, C.POINTER(_P)], C.c_int),
+    "dabs_problem_destroy": ([_P], C.c_int),
+    "dabs_problem_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
+    "dabs_energy": ([_P, _P, C.c_int32, _P, _P], C.c_int),
+    "dabs_search": ([_P, C.POINTER(dabs_search_params), C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_int32, _P, _P],
+                    C.c_int),
+    "dabs_batch_search": ([_P, C.POINTER(dabs_batch_params), C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+                          C.c_int),
+    "dabs_solver_create": ([_P, C.POINTER(dabs_ga_params), C.c_int32, _P, C.POINTER(_P)], C.c_int),
+    "dabs_solver_destroy": ([_P], C.c_int),
+    "dabs_solver_run": ([_P, C.c_int32, _P, _P], C.c_int),
+    "dabs_solver_pools": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "dabs_solver_state": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "dabs_solver_progress": ([_P, _P, _P], C.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdabs.so is not built (run __graft_entry__.build() or "
+                               "python paper_2207_03069_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != DABS_OK:
+        msg = lib().dabs_last_error().decode(errors="replace") or lib().dabs_strerror(status).decode()
+        raise DabsError(status, msg)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def dabs_strerror(status: int) -> str:
+    return lib().dabs_strerror(status).decode()
+
+
+def dabs_last_error() -> str:
+    return lib().dabs_last_error().decode()
+
+
+def dabs_max_n(wtype: int) -> int:
+    return int(lib().dabs_max_n(wtype))
+
+
+class Problem:
+    """Handle of a loaded QUBO matrix (library-owned)."""
+
+    def __init__(self, handle, n, wtype, bound):
+        self.handle, self.n, self.wtype, self.bound = handle, n, wtype, bound
+        self.nwords = (n + 63) // 64
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.dabs_problem_destroy(h)
+
+
+def dabs_problem_create(W, stream=None) -> Problem:
+    """W: square int16 or int32 CUDA tensor (row stride W.stride(0))."""
+    import torch
+    if W.dim() != 2 or W.shape[0] != W.shape[1] or W.stride(1) != 1:
+        raise ValueError("W must be a square row-major matrix")
+    wtype = {torch.int16: DABS_W_I16, torch.int32: DABS_W_I32}.get(W.dtype)
+    if wtype is None:
+        raise ValueError("W must be int16 or int32")
+    h = C.c_void_p()
+    _check(lib().dabs_problem_create(_ptr(W), W.shape[0], W.stride(0), wtype, _stream(stream), C.byref(h)))
+    n, wt, b = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().dabs_problem_info(h, C.byref(n), C.byref(wt), C.byref(b)))
+    return Problem(h, n.value, wt.value, b.value)
+
+
+def dabs_energy(p: Problem, x, e, stream=None):
+    _check(lib().dabs_energy(p.handle, _ptr(x), x.shape[0], _ptr(e), _stream(stream)))
+
+
+def dabs_search(p: Problem, params: dabs_search_params, x, target, best, best_e, e, delta=None, trace=None,
+                flips=None, stream=None):
+    cap = trace.shape[1] if trace is not None else 0
+    _check(lib().dabs_search(p.handle, C.byref(params), x.shape[0], _ptr(x), _ptr(target), _ptr(best),
+                             _ptr(best_e), _ptr(e), _ptr(delta), _ptr(trace), cap, _ptr(flips), _stream(stream)))
+
+
+def dabs_batch_search(p: Problem, params: dabs_batch_params, x, target, algo, phase, best, best_e, e, flips=None,
+                      stream=None):
+    _check(lib().dabs_batch_search(p.handle, C.byref(params), x.shape[0], _ptr(x), _ptr(target), _ptr(algo),
+                                   _ptr(phase), _ptr(best), _ptr(best_e), _ptr(e), _ptr(flips), _stream(stream)))
+
+
+class Solver:
+    def __init__(self, handle, problem, params, instances):
+        self.handle, self.problem, self.params, self.instances = handle, problem, params, instances
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.dabs_solver_destroy(h)
+
+
+def ga_params(*, T, Bn, tau=8, seed=0, capacity=100, npools=1, algos=MAIN_ALGOS, ops=tuple(range(8)),
+              p_explore=214748365, p_mutation=1 << 29, p_zero=1 << 29, p_one=1 << 29, crossover_kind=0,
+              greedy_cap=0) -> dabs_ga_params:
+    g = dabs_ga_params()
+    g.n_algos = len(algos)
+    for i, a in enumerate(algos):
+        g.algos[i] = a
+    g.n_ops = len(ops)
+    for i, o in enumerate(ops):
+        g.ops[i] = o
+    g.p_explore, g.p_mutation, g.p_zero, g.p_one = p_explore, p_mutation, p_zero, p_one
+    g.crossover_kind, g.capacity, g.npools, g.tau = crossover_kind, capacity, npools, tau
+    g.T, g.Bn, g.greedy_cap, g.seed = T, Bn, greedy_cap, seed
+    return g
+
+
+def dabs_solver_create(p: Problem, params: dabs_ga_params, instances: int, stream=None) -> Solver:
+    h = C.c_void_p()
+    _check(lib().dabs_solver_create(p.handle, C.byref(params), instances, _stream(stream), C.byref(h)))
+    return Solver(h, p, params, instances)
+
+
+def dabs_solver_run(s: Solver, rounds: int, target_e=None, stream=None):
+    _check(lib().dabs_solver_run(s.handle, rounds, _ptr(target_e), _stream(stream)))
+
+
+def dabs_solver_pools(s: Solver, bits=None, e=None, algo=None, op=None, stream=None):
+    _check(lib().dabs_solver_pools(s.handle, _ptr(bits), _ptr(e), _ptr(algo), _ptr(op), _stream(stream)))
+
+
+def dabs_solver_state(s: Solver, x=None, e=None, phase=None, total_flips=None, stream=None):
+    _check(lib().dabs_solver_state(s.handle, _ptr(x), _ptr(e), _ptr(phase), _ptr(total_flips), _stream(stream)))
+
+
+def dabs_solver_progress(s: Solver, out, stream=None):
+    _check(lib().dabs_solver_progress(s.handle, _ptr(out), _stream(stream)))

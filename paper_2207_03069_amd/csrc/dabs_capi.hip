@@ -1,0 +1,282 @@
+// dabs_capi.hip -- C-ABI of the bulk-search library: problem load and
+// validation, energies from scratch, search and batch-search launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "dabs_internal.h"
+#include "dabs_device.h"
+
+static thread_local char g_err[512];
+
+int dabs_fail(int status, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+#define HIP_OK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return dabs_fail(DABS_E_HIP, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+namespace dabs {
+
+// Symmetry and delta bound of the caller's W: one block per row i; every
+// thread compares its W_ij with W_ji and sums |W_ij| (counted twice off the
+// diagonal).
+template <typename WT>
+__global__ __launch_bounds__(256) void k_validate(const WT *__restrict__ W, int64_t ld, int n,
+                                                  int *__restrict__ bad, long long *__restrict__ rowb) {
+    const int i = blockIdx.x;
+    long long acc = 0;
+    int asym = 0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const long long a = W[(int64_t)i * ld + j], b = W[(int64_t)j * ld + i];
+        asym |= a != b;
+        acc += (j == i ? 1 : 2) * (a < 0 ? -a : a);
+    }
+    __shared__ long long part[256];
+    __shared__ int pbad[256];
+    part[threadIdx.x] = acc;
+    pbad[threadIdx.x] = asym;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            part[threadIdx.x] += part[threadIdx.x + s];
+            pbad[threadIdx.x] |= pbad[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        rowb[i] = part[0];
+        if (pbad[0]) atomicOr(bad, 1);
+    }
+}
+
+// Library layout: rows of length ld (multiple of 512) with a zero diagonal and
+// zero padding; the diagonal goes to its own array.
+template <typename WT>
+__global__ __launch_bounds__(256) void k_pack(const WT *__restrict__ W, int64_t ldin, int n, WT *__restrict__ out,
+                                              int64_t ld, int *__restrict__ diag) {
+    const int i = blockIdx.y;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ld; j += (int64_t)gridDim.x * blockDim.x) {
+        WT v = 0;
+        if (j < n) v = W[(int64_t)i * ldin + j];
+        if (j == i) {
+            diag[i] = (int)v;
+            v = 0;
+        }
+        out[(int64_t)i * ld + j] = v;
+    }
+}
+
+// E(X) = sum_i x_i (W_ii + sum_{j != i} W_ij x_j) from scratch, one wave per
+// vector; lane l handles columns l, l+64, ...
+template <typename WT>
+__global__ __launch_bounds__(256) void k_energy(const WT *__restrict__ W, const int *__restrict__ diag, int64_t ld,
+                                                int n, int nwords, const uint64_t *__restrict__ x, int count,
+                                                int64_t *__restrict__ e) {
+    const int wid = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (wid >= count) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t *xv = x + (int64_t)wid * nwords;
+    long long acc = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!((xv[i >> 6] >> (i & 63)) & 1)) continue;
+        if (lane == 0) acc += diag[i];
+        for (int w = 0; w < nwords; ++w) {
+            const int j = w * 64 + lane;
+            if (j < n && ((xv[w] >> lane) & 1)) acc += W[(int64_t)i * ld + j];
+        }
+    }
+    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane == 0) e[wid] = acc;
+}
+
+}  // namespace dabs
+
+using namespace dabs;
+
+extern "C" {
+
+const char *dabs_strerror(int status) {
+    switch (status) {
+    case DABS_OK: return "ok";
+    case DABS_E_INVALID: return "invalid argument";
+    case DABS_E_NOT_SYMMETRIC: return "W is not symmetric";
+    case DABS_E_RANGE: return "W exceeds the exact device range (delta bound >= 2^23 - 1)";
+    case DABS_E_NOMEM: return "device allocation failed";
+    case DABS_E_HIP: return "HIP runtime error";
+    case DABS_E_UNSUPPORTED: return "size not supported by this build";
+    default: return "unknown status";
+    }
+}
+
+const char *dabs_last_error(void) { return g_err; }
+
+int32_t dabs_max_n(int32_t wtype) { return dabs::max_n(wtype); }
+
+int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype, void *stream,
+                        dabs_problem **out) {
+    g_err[0] = 0;
+    if (!w_dev || !out) return dabs_fail(DABS_E_INVALID, "null pointer");
+    if (n < 1 || ld < n) return dabs_fail(DABS_E_INVALID, "need n >= 1 and ld >= n (n=%d ld=%lld)", n, (long long)ld);
+    if (wtype != DABS_W_I16 && wtype != DABS_W_I32) return dabs_fail(DABS_E_INVALID, "bad wtype %d", wtype);
+    if (n > dabs::max_n(wtype)) return dabs_fail(DABS_E_UNSUPPORTED, "n=%d above %d", n, dabs::max_n(wtype));
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    const size_t es = wtype == DABS_W_I16 ? 2 : 4;
+    const int64_t lds = ((int64_t)n + 511) / 512 * 512;
+    // the search kernels run with a power-of-two slot count; pad rows to it
+    const int64_t span = wtype == DABS_W_I16 ? 512 : 256;
+    int64_t slots = ((int64_t)n + span - 1) / span, p2 = 1;
+    while (p2 < slots) p2 <<= 1;
+    const int64_t ldp = p2 * span > lds ? p2 * span : lds;
+    int *bad = nullptr;
+    long long *rowb = nullptr;
+    void *Wp = nullptr;
+    int *diag = nullptr;
+    if (hipMalloc(&bad, sizeof(int)) != hipSuccess || hipMalloc(&rowb, sizeof(long long) * n) != hipSuccess ||
+        hipMalloc(&Wp, es * (size_t)n * (size_t)ldp) != hipSuccess || hipMalloc(&diag, sizeof(int) * n) != hipSuccess) {
+        hipFree(bad); hipFree(rowb); hipFree(Wp); hipFree(diag);
+        return dabs_fail(DABS_E_NOMEM, "allocating %zu bytes for W", es * (size_t)n * (size_t)ldp);
+    }
+    int status = DABS_OK;
+    long long *hb = (long long *)malloc(sizeof(long long) * n);
+    int hbad = 0;
+    do {
+        if (hipMemsetAsync(bad, 0, sizeof(int), st) != hipSuccess) { status = DABS_E_HIP; break; }
+        if (wtype == DABS_W_I16)
+            hipLaunchKernelGGL(k_validate<int16_t>, dim3(n), dim3(256), 0, st, (const int16_t *)w_dev, ld, n, bad, rowb);
+        else
+            hipLaunchKernelGGL(k_validate<int32_t>, dim3(n), dim3(256), 0, st, (const int32_t *)w_dev, ld, n, bad, rowb);
+        if (hipGetLastError() != hipSuccess) { status = DABS_E_HIP; break; }
+        if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hb, rowb, sizeof(long long) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) { status = DABS_E_HIP; break; }
+    } while (0);
+    long long bound = 0;
+    for (int i = 0; i < n && status == DABS_OK; ++i) bound = hb[i] > bound ? hb[i] : bound;
+    free(hb);
+    if (status == DABS_OK && hbad) status = dabs_fail(DABS_E_NOT_SYMMETRIC, "W is not symmetric");
+    if (status == DABS_OK && bound >= (1 << 23) - 1)
+        status = dabs_fail(DABS_E_RANGE, "delta bound %lld >= 2^23 - 1", bound);
+    if (status == DABS_OK) {
+        const int gx = (int)((ldp + 255) / 256);
+        if (wtype == DABS_W_I16)
+            hipLaunchKernelGGL(k_pack<int16_t>, dim3(gx, n), dim3(256), 0, st, (const int16_t *)w_dev, ld, n,
+                               (int16_t *)Wp, ldp, diag);
+        else
+            hipLaunchKernelGGL(k_pack<int32_t>, dim3(gx, n), dim3(256), 0, st, (const int32_t *)w_dev, ld, n,
+                               (int32_t *)Wp, ldp, diag);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+            status = dabs_fail(DABS_E_HIP, "packing W failed");
+    } else if (status == DABS_E_HIP) {
+        dabs_fail(DABS_E_HIP, "validating W failed");
+    }
+    hipFree(bad);
+    hipFree(rowb);
+    if (status != DABS_OK) {
+        hipFree(Wp);
+        hipFree(diag);
+        return status;
+    }
+    dabs_problem *p = new dabs_problem;
+    p->n = n;
+    p->wtype = wtype;
+    p->ld = ldp;
+    p->bound = bound;
+    p->W = Wp;
+    p->diag = diag;
+    p->device = dev;
+    *out = p;
+    return DABS_OK;
+}
+
+int dabs_problem_destroy(dabs_problem *p) {
+    if (!p) return DABS_OK;
+    hipFree(p->W);
+    hipFree(p->diag);
+    delete p;
+    return DABS_OK;
+}
+
+int dabs_problem_info(const dabs_problem *p, int32_t *n, int32_t *wtype, int64_t *bound) {
+    if (!p) return dabs_fail(DABS_E_INVALID, "null problem");
+    if (n) *n = p->n;
+    if (wtype) *wtype = p->wtype;
+    if (bound) *bound = p->bound;
+    return DABS_OK;
+}
+
+int dabs_energy(const dabs_problem *p, const uint64_t *x_dev, int32_t count, int64_t *e_dev, void *stream) {
+    if (!p || (!x_dev && count > 0) || (!e_dev && count > 0) || count < 0)
+        return dabs_fail(DABS_E_INVALID, "bad energy arguments");
+    if (count == 0) return DABS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int nw = (p->n + 63) / 64;
+    const int blocks = (count + 3) / 4;
+    if (p->wtype == DABS_W_I16)
+        hipLaunchKernelGGL(k_energy<int16_t>, dim3(blocks), dim3(256), 0, st, (const int16_t *)p->W, p->diag, p->ld,
+                           p->n, nw, x_dev, count, e_dev);
+    else
+        hipLaunchKernelGGL(k_energy<int32_t>, dim3(blocks), dim3(256), 0, st, (const int32_t *)p->W, p->diag, p->ld,
+                           p->n, nw, x_dev, count, e_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+static bool rule_ok(int r) { return r >= DABS_GREEDY && r <= DABS_TABU_GREEDY; }
+
+int dabs_search(const dabs_problem *p, const dabs_search_params *sp, int32_t count, uint64_t *x_dev,
+                const uint64_t *target_dev, uint64_t *best_dev, int64_t *best_e_dev, int64_t *e_dev,
+                int32_t *delta_dev, int32_t *trace_dev, int32_t trace_cap, int32_t *flips_dev, void *stream) {
+    if (!p || !sp) return dabs_fail(DABS_E_INVALID, "null problem or params");
+    if (count < 0) return dabs_fail(DABS_E_INVALID, "count < 0");
+    if (count == 0) return DABS_OK;
+    if (!x_dev || !best_dev || !best_e_dev || !e_dev) return dabs_fail(DABS_E_INVALID, "null output");
+    if (!rule_ok(sp->rule)) return dabs_fail(DABS_E_INVALID, "bad rule %d", sp->rule);
+    if (sp->rule == DABS_STRAIGHT && !target_dev) return dabs_fail(DABS_E_INVALID, "Straight needs targets");
+    const bool fixed = sp->rule != DABS_GREEDY && sp->rule != DABS_STRAIGHT && sp->rule != DABS_TWONEIGHBOR;
+    if (fixed && sp->T < 1) return dabs_fail(DABS_E_INVALID, "T must be >= 1");
+    if (sp->tau < 0 || sp->tau > TAU_MAX) return dabs_fail(DABS_E_INVALID, "tau must be in [0, %d]", TAU_MAX);
+    if (trace_dev && trace_cap < 1) return dabs_fail(DABS_E_INVALID, "trace_cap must be >= 1");
+    WalkArgs a;
+    memset(&a, 0, sizeof(a));
+    a.W = p->W; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
+    a.batch = 0; a.rule = sp->rule; a.T = sp->T; a.tau = sp->tau; a.greedy_cap = sp->greedy_cap;
+    a.seed = sp->seed; a.phase = sp->phase; a.inst0 = sp->inst0;
+    a.x = x_dev; a.target = target_dev; a.best = best_dev; a.best_e = best_e_dev; a.e = e_dev;
+    a.delta = delta_dev; a.trace = trace_dev; a.trace_cap = trace_cap; a.flips = flips_dev;
+    HIP_OK(launch_walk(p, a, (hipStream_t)stream));
+    return DABS_OK;
+}
+
+int dabs_batch_search(const dabs_problem *p, const dabs_batch_params *bp, int32_t count, uint64_t *x_dev,
+                      const uint64_t *target_dev, const int32_t *algo_dev, uint32_t *phase_dev, uint64_t *best_dev,
+                      int64_t *best_e_dev, int64_t *e_dev, int32_t *flips_dev, void *stream) {
+    if (!p || !bp) return dabs_fail(DABS_E_INVALID, "null problem or params");
+    if (count < 0) return dabs_fail(DABS_E_INVALID, "count < 0");
+    if (count == 0) return DABS_OK;
+    if (!x_dev || !target_dev || !algo_dev || !phase_dev || !best_dev || !best_e_dev || !e_dev)
+        return dabs_fail(DABS_E_INVALID, "null pointer");
+    if (bp->T < 1) return dabs_fail(DABS_E_INVALID, "T must be >= 1");
+    if (bp->tau < 0 || bp->tau > TAU_MAX) return dabs_fail(DABS_E_INVALID, "tau must be in [0, %d]", TAU_MAX);
+    WalkArgs a;
+    memset(&a, 0, sizeof(a));
+    a.W = p->W; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
+    a.batch = 1; a.T = bp->T; a.Bn = bp->Bn; a.tau = bp->tau; a.greedy_cap = bp->greedy_cap;
+    a.seed = bp->seed; a.inst0 = bp->inst0;
+    a.algo = algo_dev; a.phase_arr = phase_dev;
+    a.x = x_dev; a.target = target_dev; a.best = best_dev; a.best_e = best_e_dev; a.e = e_dev; a.flips = flips_dev;
+    HIP_OK(launch_walk(p, a, (hipStream_t)stream));
+    return DABS_OK;
+}
+
+}  // extern "C"

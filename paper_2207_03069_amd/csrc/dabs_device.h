@@ -1,0 +1,116 @@
+// dabs_device.h -- device-side building blocks of the bulk-search kernels
+// (gfx950, wave64): counter-based generator, wave reductions, and the
+// per-wave search instance ("walker") that keeps one instance's state in
+// registers.
+//
+// Data layout of one instance inside a wave.  W rows are read as 16-byte
+// vectors: V = 16 / sizeof(weight) elements per lane per slot, SLOTS slots
+// cover n.  Lane l holds, for slot s and sub-index e < V, bit
+// k = s*64*V + l*V + e at local index j = s*V + e.  Per element the lane keeps
+//   h[j]  the local field  W_kk + 2 sum_{m != k} W_km x_m  (so that
+//         Delta_k = (1 - 2 x_k) h_k, Section III-A Eq. (3) in the full-sum
+//         convention), updated on a flip of bit i by h_k += 2 (1 - 2 x_i) W_ik
+//         (Eq. (4); the device copy of W has a zero diagonal, so h_i itself is
+//         unchanged, which is Eq. (5) once x_i flips);
+//   s2[j] (1 - 2 x_k) * 2^KB, so that key_j = h_j * s2_j + j = Delta_k 2^KB + j
+//         is one 24-bit multiply-add and orders by (Delta, k) within the lane;
+//   pen[j] 0, or PEN when the element is excluded from the rule's domain
+//         (tabu, or equal to the Straight target).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dabs {
+
+constexpr int WAVE = 64;
+constexpr int H_PAD = (1 << 23) - 1;     // local field of padding elements
+constexpr int PEN = 1 << 30;             // additive key penalty of excluded elements
+constexpr int KEY_BIG = 0x7fffffff;
+constexpr int TAU_MAX = 16;
+constexpr int64_t E_INF = INT64_MAX;
+
+enum Rule { GREEDY = 0, STRAIGHT = 1, MAXMIN = 2, CYCLICMIN = 3, RANDOMMIN = 4,
+            POSITIVEMIN = 5, TWONEIGHBOR = 6, TABU_GREEDY = 7 };
+enum Tag { TAG_MAXMIN = 1, TAG_POSMIN = 2, TAG_RANDMIN = 3, TAG_GA = 4, TAG_POOL = 5 };
+
+constexpr int clog2(int v) { return v <= 1 ? 0 : 1 + clog2((v + 1) / 2); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten S-box rounds on a
+// 128-bit counter, key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct R4 { uint32_t w[4]; };
+
+__device__ __forceinline__ R4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint64_t key) {
+    uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    R4 r; r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
+    return r;
+}
+
+__device__ __forceinline__ uint32_t scale32(uint32_t u, uint32_t m) {
+    return (uint32_t)(((uint64_t)u * (uint64_t)m) >> 32);
+}
+
+// 32.32 fixed-point cube, floor-chained.
+__device__ __forceinline__ uint64_t cube_frac(uint64_t f) { return (((f * f) >> 32) * f) >> 32; }
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() {
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+// Row-level butterflies (quad xor 1, quad xor 2, half mirror, mirror) leave
+// each 16-lane row with its extremum; the four rows are combined in SGPRs.
+template <bool MAX>
+__device__ __forceinline__ int wave_ext(int v) {
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+    const int a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
+    return op(op(a, b), op(c, d));
+}
+__device__ __forceinline__ int wave_min(int v) { return wave_ext<false>(v); }
+__device__ __forceinline__ int wave_max(int v) { return wave_ext<true>(v); }
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+    int lo = __shfl_xor((int)(uint32_t)v, m, WAVE), hi = __shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ long long wave_sum64(long long v) {
+    for (int m = 1; m < WAVE; m <<= 1) v += (long long)shfl_xor64((uint64_t)v, m);
+    return v;
+}
+
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+    // sign-extension from 24 bits is a no-op for |a|,|b| < 2^23 and lets the
+    // compiler emit one v_mad_i32_i24
+    return ((a << 8) >> 8) * ((b << 8) >> 8) + c;
+}
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+}  // namespace dabs

@@ -1,0 +1,55 @@
+// dabs_internal.h -- host-side structures shared by the library's translation
+// units (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dabs.h"
+
+struct dabs_problem {
+    int32_t n;
+    int32_t wtype;       // dabs_wtype
+    int64_t ld;          // padded row stride (elements), multiple of 512
+    int64_t bound;       // max_k |W_kk| + 2 sum_{j!=k} |W_kj|
+    void *W;             // device, n rows x ld, zero diagonal, zero padding
+    int32_t *diag;       // device, n
+    int device;
+};
+
+namespace dabs {
+
+// Kernel arguments of the per-wave search kernels.
+struct WalkArgs {
+    const void *W;
+    const int32_t *diag;
+    int64_t ld;
+    int32_t n, nwords, count;
+    int32_t batch;               // 0: one phase of `rule`; 1: batch search
+    int32_t rule, T, Bn, tau, greedy_cap;
+    uint64_t seed;
+    uint32_t phase, inst0;
+    const int32_t *algo;         // batch: main rule per instance
+    uint32_t *phase_arr;         // batch: per-instance phase counters (in/out)
+    uint64_t *x;                 // [count][nwords] in/out
+    const uint64_t *target;      // [count][nwords]
+    uint64_t *best;              // [count][nwords]
+    int64_t *best_e, *e;         // [count]
+    int32_t *delta;              // nullable [count][n]
+    int32_t *trace;              // nullable [count][trace_cap]
+    int32_t trace_cap;
+    int32_t *flips;              // nullable [count]
+    long long *flip_total;       // nullable: atomic sum of flips
+    const int64_t *target_e;     // nullable: time-to-target energy
+    unsigned long long *hit;     // first-hit ticks (atomicMin), with target_e
+    const unsigned long long *t0;
+};
+
+// Launches the walker kernel matching the problem's weight type and size.
+hipError_t launch_walk(const dabs_problem *p, const WalkArgs &a, hipStream_t stream);
+// Largest n the walker kernels support for a weight type.
+int max_n(int wtype);
+
+}  // namespace dabs
+
+// Thread-local error text (dabs_capi.hip).
+int dabs_fail(int status, const char *fmt, ...);

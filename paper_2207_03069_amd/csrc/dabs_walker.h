@@ -1,0 +1,646 @@
+// dabs_walker.h -- one search instance per wavefront (Section III-A, B).
+//
+// The walker keeps X, the local fields, BEST and the energies of one instance
+// in the registers of one wave (layout in dabs_device.h).  Every flip reads
+// one row of W (16-byte loads, one per slot) and updates the local fields with
+// one v_dot2 (int16) or v_mad_i32_i24 (int32) per element; the argmin over
+// the deltas is a per-lane min3 chain over packed (delta, index) keys followed
+// by a DPP wave reduction.  Step 1 (BEST) runs at every visited state.
+#pragma once
+#include "dabs_device.h"
+
+namespace dabs {
+
+struct Sel {
+    int d;   // delta of the selected bit
+    int i;   // global bit index
+    int L;   // lane holding it
+    int j;   // local index inside that lane
+};
+
+template <typename WT, int SLOTS>
+struct Walker {
+    static constexpr int V = 16 / (int)sizeof(WT);
+    static constexpr int LOGV = V == 8 ? 3 : 2;
+    static constexpr int EPL = V * SLOTS;
+    static constexpr int KB = clog2(EPL) < LOGV ? LOGV : clog2(EPL);
+    static constexpr int SB = KB - LOGV;
+    static constexpr int SPAN = WAVE * V;   // bits covered by one slot
+    typedef int vecE __attribute__((ext_vector_type(EPL)));
+
+    // The per-element vectors are the kernel's own local variables, one flat
+    // vector each (element j = s*V + e), which keeps them in registers and
+    // turns a uniform dynamic index into s_set_gpr_idx; the walker refers to
+    // them.
+    vecE &h, &s2, &pen, &key;
+
+    __device__ __forceinline__ Walker(vecE &h_, vecE &s2_, vecE &pen_, vecE &key_)
+        : h(h_), s2(s2_), pen(pen_), key(key_) {}
+    const WT *__restrict__ W;
+    int64_t ld;
+    int n, lane;
+    uint64_t xb, bb;          // X and BEST bits of this lane (bit j)
+    uint64_t vb;              // valid-element bits of this lane (bit j set iff bit index < n)
+    int64_t E, Eb;
+    // Step 1 state of the current vector
+    int kminU, mU;
+    // time to target
+    int64_t target;
+    unsigned long long *hit;
+    unsigned long long t0;
+    bool hit_done;
+    // trace
+    int *trace;
+    int trace_cap;
+    int flips;
+    // generator
+    uint64_t seed;
+    uint32_t inst;
+    // tabu ring (uniform)
+    int ring[TAU_MAX];
+    int tau;
+
+    // ---------------------------------------------------------------- layout
+    static __device__ __forceinline__ int lidx_to_lane(int i) { return (i >> LOGV) & (WAVE - 1); }
+    static __device__ __forceinline__ int lidx_of(int i) { return ((i / SPAN) << LOGV) | (i & (V - 1)); }
+    __device__ __forceinline__ int gidx(int s, int e) const { return s * SPAN + lane * V + e; }
+
+    template <class F>
+    __device__ __forceinline__ void at_slot(int s, F f) {
+#pragma unroll
+        for (int ss = 0; ss < SLOTS; ++ss)
+            if (ss == s) f(ss);
+    }
+    __device__ __forceinline__ int get_key(int j) { return key[j]; }
+    __device__ __forceinline__ void set_lane_elem(vecE &a, int j, int L, int v) {
+        const int o = a[j];
+        a[j] = lane == L ? v : o;
+    }
+    __device__ __forceinline__ void neg_lane_elem(vecE &a, int j, int L) {
+        const int o = a[j];
+        a[j] = lane == L ? -o : o;
+    }
+
+    // ------------------------------------------------------------- set up
+    __device__ __forceinline__ void setup(const WT *Wp, const int *diag, int64_t ld_, int n_, uint64_t seed_, uint32_t inst_) {
+        W = Wp; ld = ld_; n = n_; seed = seed_; inst = inst_;
+        lane = lane_id();
+        vb = 0;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (gidx(s, e) < n) vb |= 1ull << (s * V + e);
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int k = gidx(s, e);
+                h[s * V + e] = k < n ? diag[k] : H_PAD;          // X = 0: Delta_k = W_kk
+                s2[s * V + e] = 1 << KB;
+                pen[s * V + e] = k < n ? 0 : PEN;           // padding never enters a domain
+            }
+        xb = 0; bb = 0; E = 0; Eb = 0;
+        hit = nullptr; hit_done = true; target = 0; t0 = 0;
+        trace = nullptr; trace_cap = 0; flips = 0;
+        tau = 0;
+#pragma unroll
+        for (int q = 0; q < TAU_MAX; ++q) ring[q] = -1;
+    }
+
+    // h_k += c W_ik for all k (row i of the zero-diagonal copy of W).
+    __device__ __forceinline__ void update_row(int i, int c) {
+        if ((unsigned)i >= (unsigned)n) i = 0;     // never read outside W (a selection bug shows in parity)
+        const WT *row = W + (int64_t)i * ld + lane * V;
+        uint4 q[SLOTS];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            q[s] = make_uint4(0, 0, 0, 0);
+            if (s * SPAN + lane * V < n) q[s] = *(const uint4 *)(row + s * SPAN);
+        }
+        if constexpr (sizeof(WT) == 2) {
+            const short2v clo = {(short)c, 0}, chi = {0, (short)c};
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const uint32_t d[4] = {q[s].x, q[s].y, q[s].z, q[s].w};
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const short2v w2 = __builtin_bit_cast(short2v, d[p]);
+                    h[s * V + 2 * p] = __builtin_amdgcn_sdot2(w2, clo, h[s * V + 2 * p], false);
+                    h[s * V + 2 * p + 1] = __builtin_amdgcn_sdot2(w2, chi, h[s * V + 2 * p + 1], false);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const uint32_t d[4] = {q[s].x, q[s].y, q[s].z, q[s].w};
+#pragma unroll
+                for (int p = 0; p < 4; ++p) h[s * V + p] = mad24((int)d[p], c, h[s * V + p]);
+            }
+        }
+    }
+
+    // Flip bit i of X without Step 1 (set-up walk from X = 0).
+    __device__ __forceinline__ void raw_flip(int i) {
+        const int L = lidx_to_lane(i), j = lidx_of(i);
+        const int xi = (int)((readlane64(xb, L) >> j) & 1);
+        int hv = 0;
+        hv = h[j];
+        const int hi = readlane(hv, L);
+        E += xi ? -hi : hi;
+        update_row(i, xi ? -2 : 2);
+        neg_lane_elem(s2, j, L);
+        xb ^= lane == L ? (1ull << j) : 0ull;
+    }
+
+    // X := x (packed words), walking from X = 0 by flips in increasing index.
+    __device__ __forceinline__ void load_x(const uint64_t *x) {
+        const int nw = (n + 63) / 64;
+        for (int w = 0; w < nw; ++w) {
+            uint64_t word = x[w];
+            if (w == nw - 1 && (n & 63)) word &= (1ull << (n & 63)) - 1;   // bits >= n are ignored
+            while (word) {
+                const int b = __builtin_ctzll(word);
+                word &= word - 1;
+                raw_flip(w * 64 + b);
+            }
+        }
+    }
+
+    // Bits of this lane as packed words (bit field gather across lanes).
+    __device__ __forceinline__ void store_bits(uint64_t bits, uint64_t *out) const {
+        const int nw = (n + 63) / 64;
+        constexpr int LPW = WAVE / V;     // lanes per 64-bit word within a slot
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            uint64_t v = ((bits >> (s * V)) & ((1ull << V) - 1)) << ((lane % LPW) * V);
+            for (int m = 1; m < LPW; m <<= 1) v |= shfl_xor64(v, m);
+            const int w = s * (SPAN / 64) + lane / LPW;
+            if (lane % LPW == 0 && w < nw) out[w] = v;
+        }
+    }
+
+    __device__ __forceinline__ void store_delta(int *out) const {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int k = gidx(s, e);
+                if (k < n) out[k] = s2[s * V + e] > 0 ? h[s * V + e] : -h[s * V + e];
+            }
+    }
+
+    // ------------------------------------------------------------- keys
+    __device__ __forceinline__ void compute_keys() {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+            for (int e = 0; e < V; ++e) key[s * V + e] = mad24(h[s * V + e], s2[s * V + e], s * V + e);
+    }
+    __device__ __forceinline__ int lane_min_key() const {
+        int m = KEY_BIG;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+            for (int e = 0; e < V; ++e) m = min(m, key[s * V + e]);
+        return m;
+    }
+    __device__ __forceinline__ int lane_min_key_pen() const {
+        int m = KEY_BIG;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+            for (int e = 0; e < V; ++e) m = min(m, key[s * V + e] + pen[s * V + e]);
+        return m;
+    }
+
+    // Wave argmin of per-lane minimum keys: lowest (delta, global index).
+    __device__ __forceinline__ Sel argmin_from(int kmin, int m) const {
+        const uint64_t bal = ballot((kmin >> LOGV) == m);
+        const int L = (int)__builtin_ctzll(bal);
+        const int kl = readlane(kmin, L);
+        const int slot = m & ((1 << SB) - 1);
+        Sel r;
+        r.d = m >> SB;
+        r.j = (slot << LOGV) | (kl & (V - 1));
+        r.i = slot * SPAN + L * V + (kl & (V - 1));
+        r.L = L;
+        return r;
+    }
+    __device__ __forceinline__ Sel wave_argmin(int kmin) const {
+        return argmin_from(kmin, wave_min(kmin >> LOGV));
+    }
+
+    __device__ __forceinline__ void note_best() {
+        if (!hit_done && Eb <= target) {
+            hit_done = true;
+            const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+            if (lane == 0) atomicMin(hit, now - t0);
+        }
+    }
+
+    // Keys of the current state, then Step 1: BEST <- best 1-bit neighbour
+    // when strictly better than E(BEST).
+    __device__ __forceinline__ void refresh() {
+        compute_keys();
+        kminU = lane_min_key();
+        mU = wave_min(kminU >> LOGV);
+        const int d = mU >> SB;
+        if (E + d < Eb) {
+            const Sel s = argmin_from(kminU, mU);
+            Eb = E + d;
+            bb = xb ^ (lane == s.L ? (1ull << s.j) : 0ull);
+            note_best();
+        }
+    }
+
+    // BEST := X, then Step 1.
+    __device__ __forceinline__ void begin() {
+        bb = xb;
+        Eb = E;
+        note_best();
+        refresh();
+    }
+
+    // Step 3: flip the selected bit, update E and every local field.
+    __device__ __forceinline__ void flip(const Sel &s) {
+        E += s.d;
+        update_row(s.i, s2_sign_at(s) > 0 ? 2 : -2);
+        neg_lane_elem(s2, s.j, s.L);
+        xb ^= lane == s.L ? (1ull << s.j) : 0ull;
+        if (trace && flips < trace_cap && lane == 0) trace[flips] = s.i;
+        flips++;
+        refresh();
+    }
+    // sign (1 - 2 x_i) of the selected element, from the X bits of its lane
+    __device__ __forceinline__ int s2_sign_at(const Sel &s) {
+        return ((readlane64(xb, s.L) >> s.j) & 1) ? -1 : 1;
+    }
+
+    __device__ __forceinline__ Sel sel_of(int i) {
+        Sel s;
+        s.i = i;
+        s.L = lidx_to_lane(i);
+        s.j = lidx_of(i);
+        s.d = readlane(get_key(s.j), s.L) >> KB;
+        return s;
+    }
+
+    // ------------------------------------------------------------- tabu
+    __device__ __forceinline__ void pen_reset() {
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) pen[j] = ((vb >> j) & 1) ? 0 : PEN;
+    }
+    __device__ __forceinline__ void tabu_reset(int tau_) {
+        tau = tau_ < 0 ? 0 : (tau_ > TAU_MAX ? TAU_MAX : tau_);
+#pragma unroll
+        for (int q = 0; q < TAU_MAX; ++q) ring[q] = -1;
+        pen_reset();
+    }
+    // After flipping i at iteration t: i becomes tabu for t+1..t+tau; the flip
+    // of iteration t-tau leaves the list unless repeated since.
+    __device__ __forceinline__ void tabu_push(const Sel &s) {
+        if (tau == 0) return;
+        int old = -1;
+#pragma unroll
+        for (int q = 0; q < TAU_MAX; ++q)
+            if (q == tau - 1) old = ring[q];
+#pragma unroll
+        for (int q = TAU_MAX - 1; q > 0; --q) ring[q] = ring[q - 1];
+        ring[0] = s.i;
+        set_lane_elem(pen, s.j, s.L, PEN);
+        if (old >= 0) {
+            bool again = false;
+#pragma unroll
+            for (int q = 0; q < TAU_MAX; ++q)
+                if (q < tau && ring[q] == old) again = true;
+            if (!again) set_lane_elem(pen, lidx_of(old), lidx_to_lane(old), 0);
+        }
+    }
+
+    // ------------------------------------------------------------- rules
+    // Greedy (Section III-A.1): flip argmin while it is negative.
+    __device__ __forceinline__ int phase_greedy(int cap) {
+        if (cap <= 0) cap = 64 * n;                   // documented default bound
+        int f = 0;
+        while (true) {
+            if ((mU >> SB) >= 0 || f >= cap) break;
+            flip(argmin_from(kminU, mU));
+            f++;
+        }
+        return f;
+    }
+
+    // Straight (Section III-A.2): argmin over bits differing from the target.
+    __device__ __forceinline__ int phase_straight(const uint64_t *target_bits) {
+        // target bits of this lane, then pen = PEN where x == d
+        const int nw = (n + 63) / 64;
+        uint64_t db = 0;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int k0 = s * SPAN + lane * V;
+            const int w = k0 >> 6;
+            const uint64_t word = w < nw ? target_bits[w] : 0ull;
+            uint64_t f = (word >> (k0 & 63)) & ((1ull << V) - 1);
+            f &= vb >> (s * V);                              // bits >= n are ignored
+            db |= f << (s * V);
+        }
+        const uint64_t diff = (xb ^ db);
+        int hd = 0;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const bool dif = (diff >> (s * V + e)) & 1;
+                pen[s * V + e] = dif ? 0 : PEN;
+                hd += dif;
+            }
+        hd = (int)wave_sum64(hd);
+        int f = 0;
+        for (; f < hd; ++f) {
+            const Sel s = wave_argmin(lane_min_key_pen());
+            set_lane_elem(pen, s.j, s.L, PEN);
+            flip(s);
+        }
+        pen_reset();
+        return f;
+    }
+
+    // Tabu greedy: T iterations of the non-tabu argmin.
+    __device__ __forceinline__ int phase_tabu_greedy(int T, int tau_) {
+        tabu_reset(tau_);
+        for (int t = 1; t <= T; ++t) {
+            const int km = lane_min_key_pen();
+            const int m = wave_min(km >> LOGV);
+            const Sel s = (m >> SB) >= H_PAD ? argmin_from(kminU, mU) : argmin_from(km, m);
+            flip(s);
+            tabu_push(s);
+        }
+        tabu_reset(0);
+        return T;
+    }
+
+    // CyclicMin (Section III-A.4): argmin over a sliding cyclic window.
+    __device__ __forceinline__ int phase_cyclicmin(int T, int tau_) {
+        tabu_reset(tau_);
+        int pos = 0;
+        for (int t = 1; t <= T; ++t) {
+            int w;
+            if (t >= T) {
+                w = n;
+            } else {
+                const uint64_t hh = ((uint64_t)t << 32) / (uint64_t)T;
+                const int c = n < 32 ? n : 32;
+                const int64_t ww = (int64_t)(((uint64_t)n * cube_frac(hh)) >> 32);
+                w = ww < c ? c : (ww > n ? n : (int)ww);
+            }
+            const bool wrap = pos + w > n;
+            const int lo = wrap ? pos + w - n : pos;       // start of the excluded / included range
+            const uint32_t span = wrap ? (uint32_t)(n - w) : (uint32_t)w;
+            int km = KEY_BIG, kw = KEY_BIG;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const uint32_t off = (uint32_t)(gidx(s, e) - lo);
+                    const bool in = wrap ? (off >= span) : (off < span);
+                    const int k = key[s * V + e];
+                    km = min(km, in ? k + pen[s * V + e] : KEY_BIG);
+                    kw = min(kw, in ? k : KEY_BIG);
+                }
+            int m = wave_min(km >> LOGV);
+            Sel s;
+            if ((m >> SB) >= H_PAD) s = wave_argmin(kw);
+            else s = argmin_from(km, m);
+            flip(s);
+            tabu_push(s);
+            pos = (pos + w) % n;
+        }
+        tabu_reset(0);
+        return T;
+    }
+
+    // Least non-tabu key per lane, or the unmasked one when every bit is tabu.
+    __device__ __forceinline__ void domain(int &km, int &mm, bool &use_pen) {
+        km = lane_min_key_pen();
+        mm = wave_min(km >> LOGV);
+        use_pen = (mm >> SB) < H_PAD;
+        if (!use_pen) { km = kminU; mm = mU; }
+    }
+
+    // Candidates: elements whose key (+ penalty) is <= dk.  Counts them, draws
+    // r = floor(v * count / 2^32) and returns the r-th candidate (0-based, in
+    // increasing bit index: slot, then lane, then sub-index).
+    __device__ __forceinline__ Sel pick_rth(int dk, bool use_pen, uint32_t v) {
+        uint32_t cs[SLOTS];
+        uint32_t c = 0;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            cs[s] = 0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int k = key[s * V + e] + (use_pen ? pen[s * V + e] : 0);
+                cs[s] += (uint32_t)__builtin_popcountll(ballot(k <= dk));
+            }
+            c += cs[s];
+        }
+        if (c == 0) return argmin_from(kminU, mU);   // cannot happen: the domain minimum qualifies
+        const uint32_t r = scale32(v, c);
+        int slot = SLOTS - 1;
+        uint32_t before = 0;
+        bool found = false;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            if (!found) {
+                if (r < before + cs[s]) { slot = s; found = true; }
+                else before += cs[s];
+            }
+        }
+        const uint32_t rr = r - before;
+        Sel out;
+        out.L = 0; out.j = 0; out.i = 0;
+        at_slot(slot, [&](int ss) {
+            uint64_t cm[V];
+            int cnt = 0;
+            uint32_t excl = 0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int k = key[ss * V + e] + (use_pen ? pen[ss * V + e] : 0);
+                cm[e] = ballot(k <= dk);
+                cnt += __builtin_amdgcn_inverse_ballot_w64(cm[e]) ? 1 : 0;
+                excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm[e] >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)cm[e], excl));
+            }
+            const uint64_t own = ballot(excl <= rr && rr < excl + (uint32_t)cnt);
+            const int L = own ? (int)__builtin_ctzll(own) : 0;
+            int left = (int)(rr - (uint32_t)readlane((int)excl, L));
+            int e_sel = 0;
+            bool got = false;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if (!got && ((cm[e] >> L) & 1)) {
+                    if (left == 0) { e_sel = e; got = true; }
+                    else left--;
+                }
+            }
+            out.L = L;
+            out.j = ss * V + e_sel;
+            out.i = ss * SPAN + L * V + e_sel;
+        });
+        out.d = readlane(get_key(out.j), out.L) >> KB;
+        return out;
+    }
+
+    // MaxMin (Section III-A.3).
+    __device__ __forceinline__ int phase_maxmin(int T, int tau_, uint32_t ph) {
+        tabu_reset(tau_);
+        for (int t = 1; t <= T; ++t) {
+            int km, mm;
+            bool use_pen;
+            domain(km, mm, use_pen);
+            const int mind = mm >> SB;
+            // max delta over the domain (padding and tabu excluded)
+            int kx = -KEY_BIG;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    // padding carries PEN permanently; tabu bits carry it while tabu
+                    const bool valid = (vb >> (s * V + e)) & 1;
+                    const int k = use_pen ? key[s * V + e] - pen[s * V + e]
+                                          : (valid ? key[s * V + e] : -KEY_BIG);
+                    kx = max(kx, k);
+                }
+            const int maxd = wave_max(kx) >> KB;
+            const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
+            const uint64_t g = ((uint64_t)(T - t) << 32) / (uint64_t)T;
+            const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cube_frac(g)) >> 32;
+            const int d = mind + (int)(((uint64_t)r.w[0] * (span + 1)) >> 32);
+            const int dk = d * (1 << KB) + ((1 << KB) - 1);
+            const Sel s = pick_rth(dk, use_pen, r.w[1]);
+            flip(s);
+            tabu_push(s);
+        }
+        tabu_reset(0);
+        return T;
+    }
+
+    // PositiveMin (Section III-A.6).
+    __device__ __forceinline__ int phase_positivemin(int T, int tau_, uint32_t ph) {
+        tabu_reset(tau_);
+        for (int t = 1; t <= T; ++t) {
+            int km, mm;
+            bool use_pen;
+            domain(km, mm, use_pen);
+            int kp = KEY_BIG;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int k = key[s * V + e] + (use_pen ? pen[s * V + e] : 0);
+                    kp = min(kp, k >= (1 << KB) ? k : KEY_BIG);
+                }
+            const int pd = wave_min(kp >> LOGV) >> SB;
+            const int d = pd >= H_PAD ? H_PAD - 1 : pd;
+            const int dk = d * (1 << KB) + ((1 << KB) - 1);
+            const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_POSMIN << 24, seed);
+            const Sel s = pick_rth(dk, use_pen, r.w[0]);
+            flip(s);
+            tabu_push(s);
+        }
+        tabu_reset(0);
+        return T;
+    }
+
+    // RandomMin (Section III-A.5): candidates by random byte < q(t).
+    __device__ __forceinline__ int phase_randommin(int T, int tau_, uint32_t ph) {
+        tabu_reset(tau_);
+        for (int t = 1; t <= T; ++t) {
+            int q;
+            if (t >= T) {
+                q = 256;
+            } else {
+                const uint64_t hh = ((uint64_t)t << 32) / (uint64_t)T;
+                const int qq = (int)(cube_frac(hh) >> 24);
+                const int qmin = (8192 + n - 1) / n;
+                q = qq < qmin ? qmin : (qq > 256 ? 256 : qq);
+            }
+            int kr = KEY_BIG;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int k0 = s * SPAN + lane * V;
+                const R4 r = philox((uint32_t)t, inst, ph, ((uint32_t)TAG_RANDMIN << 24) | (uint32_t)(k0 >> 4), seed);
+                // this lane's V bytes start at byte (k0 mod 16) of the draw
+                const int w0 = (k0 & 15) >> 2;
+                const uint32_t wa = w0 == 0 ? r.w[0] : (w0 == 1 ? r.w[1] : (w0 == 2 ? r.w[2] : r.w[3]));
+                const uint32_t wb = w0 == 0 ? r.w[1] : (w0 == 1 ? r.w[2] : r.w[3]);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const uint32_t word = e < 4 ? wa : wb;
+                    const int byte = (int)((word >> (8 * (e & 3))) & 0xFFu);
+                    const int k = key[s * V + e] + pen[s * V + e];
+                    kr = min(kr, byte < q ? k : KEY_BIG);
+                }
+            }
+            const int m = wave_min(kr >> LOGV);
+            Sel s;
+            if ((m >> SB) < H_PAD) {
+                s = argmin_from(kr, m);
+            } else {
+                int km, mm;
+                bool use_pen;
+                domain(km, mm, use_pen);
+                s = argmin_from(km, mm);
+            }
+            flip(s);
+            tabu_push(s);
+        }
+        tabu_reset(0);
+        return T;
+    }
+
+    // TwoNeighbor (Section III-A.7): 0, 1, 0, 2, 1, 3, 2, ...
+    __device__ __forceinline__ int phase_twoneighbor() {
+        flip(sel_of(0));
+        for (int k = 1; k < n; ++k) {
+            flip(sel_of(k));
+            flip(sel_of(k - 1));
+        }
+        return 2 * n - 1;
+    }
+
+    __device__ __forceinline__ int run_phase(int rule, int T, int tau_, uint32_t ph, const uint64_t *target_bits, int cap) {
+        switch (rule) {
+        case GREEDY: return phase_greedy(cap);
+        case STRAIGHT: return phase_straight(target_bits);
+        case MAXMIN: return phase_maxmin(T, tau_, ph);
+        case CYCLICMIN: return phase_cyclicmin(T, tau_);
+        case RANDOMMIN: return phase_randommin(T, tau_, ph);
+        case POSITIVEMIN: return phase_positivemin(T, tau_, ph);
+        case TWONEIGHBOR: return phase_twoneighbor();
+        case TABU_GREEDY: return phase_tabu_greedy(T, tau_);
+        default: return 0;
+        }
+    }
+
+    // Batch search (Section III-B): Straight -> Greedy -> {main -> Greedy}*.
+    __device__ __forceinline__ int batch(const uint64_t *target_bits, int rule, int T, int Bn, int tau_, uint32_t &ph, int cap) {
+        bb = xb;
+        Eb = E;
+        note_best();
+        refresh();
+        int f = phase_straight(target_bits);
+        f += phase_greedy(cap);
+        while (f < Bn) {
+            const int fm = run_phase(rule, T, tau_, ph, nullptr, cap);
+            if (fm <= 0) break;                       // not a main algorithm: stop
+            f += fm;
+            ph++;
+            f += phase_greedy(cap);
+            if (rule == TWONEIGHBOR) break;
+        }
+        return f;
+    }
+};
+
+}  // namespace dabs
