@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark of the bulk-search hot path on one MI355X.
+
+Workload (the max-cut family of Section VI-A at G-set-like shape): a random
+graph G(800, 0.06) with +-1 edge weights mapped to a QUBO (Section II-A),
+int16 W; 4096 search instances, each running the DABS loop of the paper on the
+device -- target generation by the genetic operations from 8 solution pools of
+100 entries (Section IV), batch search with s = 0.1 (T = 80 main flips) and
+b = 10 (Bn = 8000 batch flips) (Section III-B), packet insertion.  One step is
+12 generational rounds, about 10^5 flips per instance (4096 x 1e5 flips).
+
+Prints one JSON line: flips/s of the whole job (inputs resident on the device,
+W loaded before the timed region), the time to reach the best energy of the
+timed run (a rerun with the same seeds), the roofline of the batch-search
+kernel, and the CPU oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2207_03069_amd import inputs  # noqa: E402
+
+N_BITS, P_EDGE, INSTANCES = 800, 0.06, 4096
+NPOOLS, CAPACITY, TAU = 8, 100, 8
+S_FACTOR, B_FACTOR = 0.1, 10.0
+ROUNDS_PER_STEP = 12
+SEED = 0
+# int32 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def workload():
+    W, edges, w = inputs.maxcut_instance(N_BITS, P_EDGE, seed=SEED)
+    T, Bn = round(S_FACTOR * N_BITS), round(B_FACTOR * N_BITS)
+    return W, T, Bn
+
+
+def _oracle_worker(args):
+    import oracle
+    W, T, Bn, inst, seed = args
+    g = oracle.ga_params(T=T, Bn=Bn, tau=TAU, seed=seed, capacity=CAPACITY, npools=NPOOLS)
+    r = oracle.solve(W, g, inst, 1)
+    return r["flips"]
+
+
+def cpu_baseline(W, T, Bn):
+    """The CPU oracle on the host cores: independent processes, each one
+    generational round of 16 instances of the same workload (distinct seeds)."""
+    import oracle
+    oracle.build(force=False)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = [(W, T, Bn, 16, SEED + 1 + k) for k in range(cores)]
+    ctx = mp.get_context("fork")          # no GPU has been touched yet in this process
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        flips = sum(pool.map(_oracle_worker, jobs))
+    dt = time.perf_counter() - t0
+    return {"value": flips / dt, "unit": "flips/s", "cores": cores, "kind": "oracle",
+            "sample": "%d processes x (16 instances x 1 generational round), %d flips in %.1f s" %
+                      (cores, flips, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tts", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    W, T, Bn = workload()
+    cpu = None if args.no_cpu_baseline else cpu_baseline(W, T, Bn)
+
+    import torch
+    import paper_2207_03069_amd as dabs
+    dev = torch.device("cuda:0")
+    Wt = torch.from_numpy(W).to(dev)
+    prob = dabs.dabs_problem_create(Wt)
+    g = dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=SEED, capacity=CAPACITY, npools=NPOOLS,
+                       flags=dabs.DABS_SOLVER_TIME_WALK)
+    solver = dabs.dabs_solver_create(prob, g, INSTANCES)
+    for _ in range(args.warmup):
+        dabs.dabs_solver_run(solver, ROUNDS_PER_STEP)
+    torch.cuda.synchronize()
+    dabs.dabs_solver_timing(solver, reset=True)
+    tot = torch.zeros(1, dtype=torch.int64, device=dev)
+    dabs.dabs_solver_state(solver, total_flips=tot)
+    torch.cuda.synchronize()
+    f0 = int(tot.item())
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dabs.dabs_solver_run(solver, ROUNDS_PER_STEP)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    walk_ms, launches, walk_flips = dabs.dabs_solver_timing(solver, reset=True)
+    dabs.dabs_solver_state(solver, total_flips=tot)
+    prog = torch.zeros(2, dtype=torch.int64, device=dev)
+    dabs.dabs_solver_progress(solver, prog)
+    torch.cuda.synchronize()
+    flips = int(tot.item()) - f0
+    best_e = int(prog[1].item())
+
+    # roofline of the batch-search kernel: per flip it reads one row of W
+    # (n * 2 bytes) and does n multiply-adds plus n comparisons (Eq. (4) and
+    # the argmin of Steps 1-2)
+    walk_s = walk_ms / 1e3
+    bytes_per_flip = N_BITS * W.dtype.itemsize
+    ops_per_flip = 2 * N_BITS
+    achieved_ops = walk_flips * ops_per_flip / walk_s
+    roofline = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Tops/s (int32 lane-ops)", "frac": achieved_ops / VALU_PEAK_OPS, "traffic": None,
+                "kernel": "k_walk (batch search)", "launches": launches,
+                "avg_launch_ms": walk_ms / max(launches, 1),
+                "w_row_bytes_per_s": walk_flips * bytes_per_flip / walk_s / 1e9,
+                "w_row_unit": "GB/s of W rows (L2-resident, 1.28 MB)"}
+
+    tts = None
+    if not args.no_tts:
+        s2 = dabs.dabs_solver_create(prob, g, INSTANCES)
+        tgt = torch.tensor([best_e], dtype=torch.int64, device=dev)
+        hit = -1
+        t1 = time.perf_counter()
+        for _ in range(args.warmup + args.steps):
+            dabs.dabs_solver_run(s2, ROUNDS_PER_STEP, tgt)
+            dabs.dabs_solver_progress(s2, prog)
+            torch.cuda.synchronize()
+            if int(prog[0].item()) >= 0:
+                break
+        wall = time.perf_counter() - t1
+        hit = int(prog[0].item())
+        tts = {"target_e": best_e, "seconds": hit / 1e8 if hit >= 0 else None, "wall_s_incl_polling": wall,
+               "note": "first E(BEST) <= target in a rerun with the same seeds; device clock 100 MHz"}
+
+    out = {
+        "metric": "flips_per_sec_per_gpu", "value": flips / dt, "unit": "flips/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "maxcut G(800,0.06) +-1 as QUBO (int16 W), 4096 instances x ~1e5 flips per step, "
+                               "DABS generational GA (8 pools x 100), s=0.1 b=10",
+                   "n": N_BITS, "instances": INSTANCES, "rounds_per_step": ROUNDS_PER_STEP, "T": T, "Bn": Bn,
+                   "tau": TAU, "npools": NPOOLS, "capacity": CAPACITY, "flips_per_step": flips / args.steps},
+        "best_energy": best_e,
+        "time_to_target": tts,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -177,9 +177,11 @@ typedef struct {
     int32_t T;
     int32_t Bn;
     int32_t greedy_cap;
-    int32_t reserved;
+    uint32_t flags;          /* DABS_SOLVER_TIME_WALK: time every batch-search launch with HIP events */
     uint64_t seed;
 } dabs_ga_params;
+
+#define DABS_SOLVER_TIME_WALK 1u
 
 /*
  * Solver: `instances` search instances and `npools` solution pools on one
@@ -225,6 +227,16 @@ int dabs_solver_state(const dabs_solver *s, uint64_t *x_dev, int64_t *e_dev, uin
  * two int64 values written to out_dev.
  */
 int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream);
+
+/*
+ * Batch-search kernel timing of a solver created with DABS_SOLVER_TIME_WALK:
+ * out_host[0] = summed elapsed milliseconds of the batch-search launches,
+ * out_host[1] = number of launches, out_host[2] = flips they made (all since
+ * the last reset).  Synchronises on the recorded events.  reset != 0 clears
+ * the sums after reading.  DABS_E_INVALID when the solver was created
+ * without the flag.
+ */
+int dabs_solver_timing(dabs_solver *s, double *out_host, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,10 @@ class dabs_ga_params(C.Structure):
                 ("p_explore", C.c_uint32), ("p_mutation", C.c_uint32), ("p_zero", C.c_uint32),
                 ("p_one", C.c_uint32), ("crossover_kind", C.c_int32), ("capacity", C.c_int32),
                 ("npools", C.c_int32), ("tau", C.c_int32), ("T", C.c_int32), ("Bn", C.c_int32),
-                ("greedy_cap", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("greedy_cap", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64)]
+
+
+DABS_SOLVER_TIME_WALK = 1
 
 
 # every function the header declares: name -> (argtypes, restype)
@@ -68,6 +71,7 @@ _SIGS = {
     "dabs_solver_pools": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "dabs_solver_state": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "dabs_solver_progress": ([_P, _P, _P], C.c_int),
+    "dabs_solver_timing": ([_P, C.POINTER(C.c_double), C.c_int32], C.c_int),
 }
 
 _lib = None
@@ -152,6 +156,18 @@ def dabs_problem_create(W, stream=None) -> Problem:
     return Problem(h, n.value, wt.value, b.value)
 
 
+def dabs_problem_destroy(p: Problem):
+    h, p.handle = p.handle, None
+    if h:
+        _check(lib().dabs_problem_destroy(h))
+
+
+def dabs_problem_info(p: Problem):
+    n, wt, b = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().dabs_problem_info(p.handle, C.byref(n), C.byref(wt), C.byref(b)))
+    return n.value, wt.value, b.value
+
+
 def dabs_energy(p: Problem, x, e, stream=None):
     _check(lib().dabs_energy(p.handle, _ptr(x), x.shape[0], _ptr(e), _stream(stream)))
 
@@ -181,7 +197,7 @@ class Solver:
 
 def ga_params(*, T, Bn, tau=8, seed=0, capacity=100, npools=1, algos=MAIN_ALGOS, ops=tuple(range(8)),
               p_explore=214748365, p_mutation=1 << 29, p_zero=1 << 29, p_one=1 << 29, crossover_kind=0,
-              greedy_cap=0) -> dabs_ga_params:
+              greedy_cap=0, flags=0) -> dabs_ga_params:
     g = dabs_ga_params()
     g.n_algos = len(algos)
     for i, a in enumerate(algos):
@@ -191,7 +207,7 @@ def ga_params(*, T, Bn, tau=8, seed=0, capacity=100, npools=1, algos=MAIN_ALGOS,
         g.ops[i] = o
     g.p_explore, g.p_mutation, g.p_zero, g.p_one = p_explore, p_mutation, p_zero, p_one
     g.crossover_kind, g.capacity, g.npools, g.tau = crossover_kind, capacity, npools, tau
-    g.T, g.Bn, g.greedy_cap, g.seed = T, Bn, greedy_cap, seed
+    g.T, g.Bn, g.greedy_cap, g.seed, g.flags = T, Bn, greedy_cap, seed, flags
     return g
 
 
@@ -199,6 +215,12 @@ def dabs_solver_create(p: Problem, params: dabs_ga_params, instances: int, strea
     h = C.c_void_p()
     _check(lib().dabs_solver_create(p.handle, C.byref(params), instances, _stream(stream), C.byref(h)))
     return Solver(h, p, params, instances)
+
+
+def dabs_solver_destroy(s: Solver):
+    h, s.handle = s.handle, None
+    if h:
+        _check(lib().dabs_solver_destroy(h))
 
 
 def dabs_solver_run(s: Solver, rounds: int, target_e=None, stream=None):
@@ -215,3 +237,10 @@ def dabs_solver_state(s: Solver, x=None, e=None, phase=None, total_flips=None, s
 
 def dabs_solver_progress(s: Solver, out, stream=None):
     _check(lib().dabs_solver_progress(s.handle, _ptr(out), _stream(stream)))
+
+
+def dabs_solver_timing(s: Solver, reset: bool = False):
+    """(walk milliseconds, walk launches, flips) since the last reset."""
+    out = (C.c_double * 3)()
+    _check(lib().dabs_solver_timing(s.handle, out, int(reset)))
+    return out[0], int(out[1]), int(out[2])

@@ -1,0 +1,124 @@
+"""GPU parity of the device genetic algorithm (Section IV, generational
+rounds): pools (bits, energies, algorithm and operation columns) and every
+instance's state after R rounds equal the oracle's, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_03069_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2207_03069_amd as dabs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+CAP = 100000
+
+
+def run_both(W, instances, rounds, **kw):
+    n = W.shape[0]
+    g_o = oracle.ga_params(greedy_cap=CAP, **kw)
+    ref = oracle.solve(W, g_o, instances, rounds)
+    p = dabs.dabs_problem_create(torch.from_numpy(W).to(DEV))
+    g_d = dabs.ga_params(greedy_cap=CAP, **kw)
+    s = dabs.dabs_solver_create(p, g_d, instances)
+    for _ in range(rounds):                       # one round per call: rounds continue
+        dabs.dabs_solver_run(s, 1)
+    P, m, nw = g_d.npools, g_d.capacity, (n + 63) // 64
+    bits = torch.zeros((P, m, nw), dtype=torch.int64, device=DEV)
+    pe = torch.zeros((P, m), dtype=torch.int64, device=DEV)
+    pa = torch.zeros((P, m), dtype=torch.int32, device=DEV)
+    po = torch.zeros((P, m), dtype=torch.int32, device=DEV)
+    dabs.dabs_solver_pools(s, bits, pe, pa, po)
+    x = torch.zeros((instances, nw), dtype=torch.int64, device=DEV)
+    e = torch.zeros(instances, dtype=torch.int64, device=DEV)
+    ph = torch.zeros(instances, dtype=torch.int32, device=DEV)
+    tot = torch.zeros(1, dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_state(s, x, e, ph, tot)
+    torch.cuda.synchronize()
+    got = dict(pool_bits=inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), pool_e=pe.cpu().numpy(),
+               pool_algo=pa.cpu().numpy(), pool_op=po.cpu().numpy(),
+               x=inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), e=e.cpu().numpy(),
+               ph=ph.cpu().numpy().view(np.uint32), flips=int(tot.item()))
+    return got, ref
+
+
+def assert_same(got, ref):
+    for k in ("pool_e", "pool_algo", "pool_op", "pool_bits", "x", "e", "ph"):
+        assert np.array_equal(got[k], ref[k]), k
+    assert got["flips"] == ref["flips"]
+
+
+@pytest.mark.parametrize("n,wt,inst,P,rounds", [(48, np.int16, 16, 2, 3), (130, np.int16, 24, 3, 2),
+                                                (70, np.int32, 12, 1, 3), (1, np.int16, 4, 2, 2)])
+def test_solver_parity(n, wt, inst, P, rounds):
+    W = inputs.dense_qubo(n, -100, 100, 5 + n, dtype=wt)
+    got, ref = run_both(W, inst, rounds, T=max(1, n // 8), Bn=2 * n, tau=8, seed=17, capacity=10, npools=P)
+    assert_same(got, ref)
+
+
+def test_solver_parity_two_point_one_percent():
+    """The TSP workload's settings: two-point crossover, 1 % bit mutation."""
+    W = inputs.dense_qubo(96, -60, 60, 3)
+    got, ref = run_both(W, 20, 3, T=10, Bn=150, tau=8, seed=5, capacity=8, npools=2, crossover_kind=1,
+                        p_mutation=oracle.P_ONE_PERCENT)
+    assert_same(got, ref)
+
+
+@pytest.mark.parametrize("op", range(8))
+def test_solver_each_operation(op):
+    """Every genetic operation alone (p_explore = 1: uniform choice)."""
+    W, _, _ = inputs.maxcut_instance(80, 0.2, seed=op)
+    W = W.astype(np.int16)
+    got, ref = run_both(W, 10, 3, T=8, Bn=100, tau=4, seed=op, capacity=6, npools=2, ops=(op,),
+                        p_explore=2**32 - 1)
+    assert_same(got, ref)
+
+
+def test_solver_maxcut_800_sampled_round():
+    """The 800-node max-cut workload, 256 instances, 2 rounds with the full
+    operation and algorithm sets: bit-exact pools and states."""
+    W, _, _ = inputs.maxcut_instance(800, 0.06, seed=0)
+    got, ref = run_both(W, 256, 2, T=80, Bn=800, tau=8, seed=1, capacity=100, npools=8)
+    assert_same(got, ref)
+
+
+def test_time_to_target_and_progress():
+    """A reachable target energy is recorded as hit; the progress call reports
+    the best pooled energy, which equals the oracle's best after the run."""
+    W = inputs.dense_qubo(64, -100, 100, 9)
+    n = 64
+    g = dabs.ga_params(T=8, Bn=128, tau=8, seed=3, capacity=10, npools=2, greedy_cap=CAP)
+    p = dabs.dabs_problem_create(torch.from_numpy(W).to(DEV))
+    s = dabs.dabs_solver_create(p, g, 32)
+    tgt = torch.tensor([0], dtype=torch.int64, device=DEV)     # trivially reached
+    dabs.dabs_solver_run(s, 2, tgt)
+    out = torch.zeros(2, dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_progress(s, out)
+    torch.cuda.synchronize()
+    hit, best = out.cpu().numpy()
+    assert hit >= 0
+    ref = oracle.solve(W, oracle.ga_params(T=8, Bn=128, tau=8, seed=3, capacity=10, npools=2, greedy_cap=CAP), 32, 2)
+    assert best == ref["pool_e"].min()
+    unreachable = torch.tensor([-10**15], dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_run(s, 1, unreachable)
+    dabs.dabs_solver_progress(s, out)
+    torch.cuda.synchronize()
+    assert out[0].item() == -1
+    assert n == W.shape[0]
+
+
+def test_solver_errors():
+    p = dabs.dabs_problem_create(torch.from_numpy(inputs.dense_qubo(20, -5, 5, 1)).to(DEV))
+    with pytest.raises(dabs.DabsError):
+        dabs.dabs_solver_create(p, dabs.ga_params(T=0, Bn=10), 4)
+    with pytest.raises(dabs.DabsError):
+        dabs.dabs_solver_create(p, dabs.ga_params(T=2, Bn=10, algos=(dabs.DABS_GREEDY,)), 4)
+    with pytest.raises(dabs.DabsError):
+        dabs.dabs_solver_create(p, dabs.ga_params(T=2, Bn=10, capacity=0), 4)
+    with pytest.raises(dabs.DabsError):
+        dabs.dabs_solver_create(p, dabs.ga_params(T=2, Bn=10), 0)
