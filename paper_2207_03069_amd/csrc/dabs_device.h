@@ -14,8 +14,8 @@
 //         unchanged, which is Eq. (5) once x_i flips);
 //   s2[j] (1 - 2 x_k) * 2^KB, so that key_j = h_j * s2_j + j = Delta_k 2^KB + j
 //         is one 24-bit multiply-add and orders by (Delta, k) within the lane;
-//   pen[j] 0, or PEN when the element is excluded from the rule's domain
-//         (tabu, or equal to the Straight target).
+//   ex[j] the first iteration from which element j is back in the rule's
+//         domain (tabu, Straight's differing bits, padding).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,7 +24,6 @@ namespace dabs {
 
 constexpr int WAVE = 64;
 constexpr int H_PAD = (1 << 23) - 1;     // local field of padding elements
-constexpr int PEN = 1 << 30;             // additive key penalty of excluded elements
 constexpr int KEY_BIG = 0x7fffffff;
 constexpr int TAU_MAX = 16;
 constexpr int64_t E_INF = INT64_MAX;
@@ -85,14 +84,28 @@ __device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_bal
 template <bool MAX>
 __device__ __forceinline__ int wave_ext(int v) {
     auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));
     const int a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
     return op(op(a, b), op(c, d));
 }
 __device__ __forceinline__ int wave_min(int v) { return wave_ext<false>(v); }
+
+// Two wave minima reduced together so that the two DPP chains interleave.
+__device__ __forceinline__ void wave_min2(int a, int b, int &ra, int &rb) {
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0xB1, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0xB1, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x4E, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0x4E, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x141, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0x141, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x140, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0x140, 0xF, 0xF, true));
+    ra = min(min(readlane(a, 0), readlane(a, 16)), min(readlane(a, 32), readlane(a, 48)));
+    rb = min(min(readlane(b, 0), readlane(b, 16)), min(readlane(b, 32), readlane(b, 48)));
+}
 __device__ __forceinline__ int wave_max(int v) { return wave_ext<true>(v); }
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {

@@ -11,8 +11,8 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     const int wid = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     if (wid >= a.count) return;                       // whole wave leaves together
     typedef typename Walker<WT, SLOTS>::vecE vecE;
-    vecE h, s2, pen, key;
-    Walker<WT, SLOTS> w(h, s2, pen, key);
+    vecE h, s2, ex, key;
+    Walker<WT, SLOTS> w(h, s2, ex, key);
     w.setup((const WT *)a.W, a.diag, a.ld, a.n, a.seed, a.inst0 + (uint32_t)wid);
     uint64_t *x = a.x + (int64_t)wid * a.nwords;
     w.load_x(x);

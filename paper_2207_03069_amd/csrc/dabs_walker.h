@@ -6,10 +6,20 @@
 // one v_dot2 (int16) or v_mad_i32_i24 (int32) per element; the argmin over
 // the deltas is a per-lane min3 chain over packed (delta, index) keys followed
 // by a DPP wave reduction.  Step 1 (BEST) runs at every visited state.
+//
+// Rule domains (tabu, Straight's differing bits, padding) are expressed with
+// one integer per element, ex[j]: element j is outside the domain of
+// iteration t when ex[j] >= t.  Tabu sets ex[j] = t0 + tau when bit j flips
+// at iteration t0 (so it is excluded at t0+1 .. t0+tau and expires by
+// itself); padding elements hold EX_ALWAYS.  A masked key is one compare and
+// one v_cndmask per element.
 #pragma once
 #include "dabs_device.h"
 
 namespace dabs {
+
+constexpr int EX_NEVER = -(1 << 30);
+constexpr int EX_ALWAYS = 0x7fffffff;
 
 struct Sel {
     int d;   // delta of the selected bit
@@ -17,6 +27,16 @@ struct Sel {
     int L;   // lane holding it
     int j;   // local index inside that lane
 };
+
+// The selection is wave-uniform by construction; saying so keeps it in SGPRs
+// (dynamic register indexing by a VGPR value would become a waterfall loop).
+__device__ __forceinline__ Sel uniform(Sel s) {
+    s.d = __builtin_amdgcn_readfirstlane(s.d);
+    s.i = __builtin_amdgcn_readfirstlane(s.i);
+    s.L = __builtin_amdgcn_readfirstlane(s.L);
+    s.j = __builtin_amdgcn_readfirstlane(s.j);
+    return s;
+}
 
 template <typename WT, int SLOTS>
 struct Walker {
@@ -32,17 +52,19 @@ struct Walker {
     // vector each (element j = s*V + e), which keeps them in registers and
     // turns a uniform dynamic index into s_set_gpr_idx; the walker refers to
     // them.
-    vecE &h, &s2, &pen, &key;
+    vecE &h, &s2, &ex, &key;
 
-    __device__ __forceinline__ Walker(vecE &h_, vecE &s2_, vecE &pen_, vecE &key_)
-        : h(h_), s2(s2_), pen(pen_), key(key_) {}
+    __device__ __forceinline__ Walker(vecE &h_, vecE &s2_, vecE &ex_, vecE &key_)
+        : h(h_), s2(s2_), ex(ex_), key(key_) {}
+
     const WT *__restrict__ W;
     int64_t ld;
     int n, lane;
     uint64_t xb, bb;          // X and BEST bits of this lane (bit j)
     uint64_t vb;              // valid-element bits of this lane (bit j set iff bit index < n)
     int64_t E, Eb;
-    // Step 1 state of the current vector
+    // Step 1 state of the current vector: per-lane unmasked minimum key and
+    // its wave minimum (key >> LOGV)
     int kminU, mU;
     // time to target
     int64_t target;
@@ -56,9 +78,6 @@ struct Walker {
     // generator
     uint64_t seed;
     uint32_t inst;
-    // tabu ring (uniform)
-    int ring[TAU_MAX];
-    int tau;
 
     // ---------------------------------------------------------------- layout
     static __device__ __forceinline__ int lidx_to_lane(int i) { return (i >> LOGV) & (WAVE - 1); }
@@ -71,7 +90,6 @@ struct Walker {
         for (int ss = 0; ss < SLOTS; ++ss)
             if (ss == s) f(ss);
     }
-    __device__ __forceinline__ int get_key(int j) { return key[j]; }
     __device__ __forceinline__ void set_lane_elem(vecE &a, int j, int L, int v) {
         const int o = a[j];
         a[j] = lane == L ? v : o;
@@ -82,42 +100,39 @@ struct Walker {
     }
 
     // ------------------------------------------------------------- set up
-    __device__ __forceinline__ void setup(const WT *Wp, const int *diag, int64_t ld_, int n_, uint64_t seed_, uint32_t inst_) {
+    __device__ __forceinline__ void setup(const WT *Wp, const int *diag, int64_t ld_, int n_, uint64_t seed_,
+                                          uint32_t inst_) {
         W = Wp; ld = ld_; n = n_; seed = seed_; inst = inst_;
         lane = lane_id();
         vb = 0;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
-            for (int e = 0; e < V; ++e)
-                if (gidx(s, e) < n) vb |= 1ull << (s * V + e);
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s)
-#pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int k = gidx(s, e);
-                h[s * V + e] = k < n ? diag[k] : H_PAD;          // X = 0: Delta_k = W_kk
+                if (k < n) vb |= 1ull << (s * V + e);
+                h[s * V + e] = k < n ? diag[k] : H_PAD;      // X = 0: Delta_k = W_kk
                 s2[s * V + e] = 1 << KB;
-                pen[s * V + e] = k < n ? 0 : PEN;           // padding never enters a domain
+                ex[s * V + e] = k < n ? EX_NEVER : EX_ALWAYS;
             }
         xb = 0; bb = 0; E = 0; Eb = 0;
         hit = nullptr; hit_done = true; target = 0; t0 = 0;
         trace = nullptr; trace_cap = 0; flips = 0;
-        tau = 0;
-#pragma unroll
-        for (int q = 0; q < TAU_MAX; ++q) ring[q] = -1;
     }
 
-    // h_k += c W_ik for all k (row i of the zero-diagonal copy of W).
+    __device__ __forceinline__ void ex_reset() {
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) ex[j] = ((vb >> j) & 1) ? EX_NEVER : EX_ALWAYS;
+    }
+
+    // h_k += c W_ik for all k (row i of the zero-diagonal copy of W).  The
+    // padded rows hold zeros, so every lane loads every slot.
     __device__ __forceinline__ void update_row(int i, int c) {
         if ((unsigned)i >= (unsigned)n) i = 0;     // never read outside W (a selection bug shows in parity)
         const WT *row = W + (int64_t)i * ld + lane * V;
         uint4 q[SLOTS];
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            q[s] = make_uint4(0, 0, 0, 0);
-            if (s * SPAN + lane * V < n) q[s] = *(const uint4 *)(row + s * SPAN);
-        }
+        for (int s = 0; s < SLOTS; ++s) q[s] = *(const uint4 *)(row + s * SPAN);
         if constexpr (sizeof(WT) == 2) {
             const short2v clo = {(short)c, 0}, chi = {0, (short)c};
 #pragma unroll
@@ -144,9 +159,7 @@ struct Walker {
     __device__ __forceinline__ void raw_flip(int i) {
         const int L = lidx_to_lane(i), j = lidx_of(i);
         const int xi = (int)((readlane64(xb, L) >> j) & 1);
-        int hv = 0;
-        hv = h[j];
-        const int hi = readlane(hv, L);
+        const int hi = readlane(h[j], L);
         E += xi ? -hi : hi;
         update_row(i, xi ? -2 : 2);
         neg_lane_elem(s2, j, L);
@@ -193,24 +206,23 @@ struct Walker {
     // ------------------------------------------------------------- keys
     __device__ __forceinline__ void compute_keys() {
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s)
-#pragma unroll
-            for (int e = 0; e < V; ++e) key[s * V + e] = mad24(h[s * V + e], s2[s * V + e], s * V + e);
+        for (int j = 0; j < EPL; ++j) key[j] = mad24(h[j], s2[j], j);
     }
     __device__ __forceinline__ int lane_min_key() const {
         int m = KEY_BIG;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s)
-#pragma unroll
-            for (int e = 0; e < V; ++e) m = min(m, key[s * V + e]);
+        for (int j = 0; j < EPL; j += 2) m = min(m, min(key[j], key[j + 1]));
         return m;
     }
-    __device__ __forceinline__ int lane_min_key_pen() const {
+    // least key among elements with ex < thr
+    __device__ __forceinline__ int lane_min_dom(int thr) const {
         int m = KEY_BIG;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s)
-#pragma unroll
-            for (int e = 0; e < V; ++e) m = min(m, key[s * V + e] + pen[s * V + e]);
+        for (int j = 0; j < EPL; j += 2) {
+            const int a = ex[j] < thr ? key[j] : KEY_BIG;
+            const int b = ex[j + 1] < thr ? key[j + 1] : KEY_BIG;
+            m = min(m, min(a, b));
+        }
         return m;
     }
 
@@ -230,6 +242,9 @@ struct Walker {
     __device__ __forceinline__ Sel wave_argmin(int kmin) const {
         return argmin_from(kmin, wave_min(kmin >> LOGV));
     }
+    // wave minimum of k >> LOGV; the domain is empty when it decodes to a
+    // delta of H_PAD or more (only padding or excluded elements)
+    static __device__ __forceinline__ bool empty_dom(int m) { return (m >> SB) >= H_PAD; }
 
     __device__ __forceinline__ void note_best() {
         if (!hit_done && Eb <= target) {
@@ -239,12 +254,8 @@ struct Walker {
         }
     }
 
-    // Keys of the current state, then Step 1: BEST <- best 1-bit neighbour
-    // when strictly better than E(BEST).
-    __device__ __forceinline__ void refresh() {
-        compute_keys();
-        kminU = lane_min_key();
-        mU = wave_min(kminU >> LOGV);
+    // Step 1: BEST <- best 1-bit neighbour when strictly better than E(BEST).
+    __device__ __forceinline__ void step1() {
         const int d = mU >> SB;
         if (E + d < Eb) {
             const Sel s = argmin_from(kminU, mU);
@@ -252,6 +263,30 @@ struct Walker {
             bb = xb ^ (lane == s.L ? (1ull << s.j) : 0ull);
             note_best();
         }
+    }
+
+    // Keys of the current state, then Step 1.
+    __device__ __forceinline__ void refresh() {
+        compute_keys();
+        kminU = lane_min_key();
+        mU = wave_min(kminU >> LOGV);
+        step1();
+    }
+
+    // As refresh(), also reducing the least key of the domain ex < thr (kminM,
+    // mM) in the same pass.
+    int kminM, mM;
+    __device__ __forceinline__ void refresh_dom(int thr) {
+        compute_keys();
+        kminU = lane_min_key();
+        kminM = lane_min_dom(thr);
+        wave_min2(kminU >> LOGV, kminM >> LOGV, mU, mM);
+        step1();
+    }
+    // argmin of the domain reduced by refresh_dom, or the plain argmin when
+    // the domain is empty
+    __device__ __forceinline__ Sel dom_sel() const {
+        return empty_dom(mM) ? argmin_from(kminU, mU) : argmin_from(kminM, mM);
     }
 
     // BEST := X, then Step 1.
@@ -263,18 +298,24 @@ struct Walker {
     }
 
     // Step 3: flip the selected bit, update E and every local field.
-    __device__ __forceinline__ void flip(const Sel &s) {
+    __device__ __forceinline__ void flip_core(const Sel &s0) {
+        const Sel s = uniform(s0);
         E += s.d;
-        update_row(s.i, s2_sign_at(s) > 0 ? 2 : -2);
+        const bool xi = (readlane64(xb, s.L) >> s.j) & 1;
+        update_row(s.i, xi ? -2 : 2);
         neg_lane_elem(s2, s.j, s.L);
         xb ^= lane == s.L ? (1ull << s.j) : 0ull;
         if (trace && flips < trace_cap && lane == 0) trace[flips] = s.i;
         flips++;
+    }
+    __device__ __forceinline__ void flip(const Sel &s) {
+        flip_core(s);
         refresh();
     }
-    // sign (1 - 2 x_i) of the selected element, from the X bits of its lane
-    __device__ __forceinline__ int s2_sign_at(const Sel &s) {
-        return ((readlane64(xb, s.L) >> s.j) & 1) ? -1 : 1;
+    // flip, then refresh with the domain ex < thr of the next selection
+    __device__ __forceinline__ void flip_dom(const Sel &s, int thr) {
+        flip_core(s);
+        refresh_dom(thr);
     }
 
     __device__ __forceinline__ Sel sel_of(int i) {
@@ -282,40 +323,24 @@ struct Walker {
         s.i = i;
         s.L = lidx_to_lane(i);
         s.j = lidx_of(i);
-        s.d = readlane(get_key(s.j), s.L) >> KB;
+        s.d = readlane(key[s.j], s.L) >> KB;
         return s;
     }
 
-    // ------------------------------------------------------------- tabu
-    __device__ __forceinline__ void pen_reset() {
-#pragma unroll
-        for (int j = 0; j < EPL; ++j) pen[j] = ((vb >> j) & 1) ? 0 : PEN;
+    // tabu (R11): bit flipped at iteration t is excluded at t+1 .. t+tau
+    // (one element write in every case: a conditional write would be turned
+    // into a select over the whole vector)
+    __device__ __forceinline__ void mark_tabu(const Sel &s0, int t, int tau) {
+        const Sel s = uniform(s0);
+        const int o = ex[s.j];
+        ex[s.j] = (lane == s.L && tau > 0) ? t + tau : o;
     }
-    __device__ __forceinline__ void tabu_reset(int tau_) {
-        tau = tau_ < 0 ? 0 : (tau_ > TAU_MAX ? TAU_MAX : tau_);
-#pragma unroll
-        for (int q = 0; q < TAU_MAX; ++q) ring[q] = -1;
-        pen_reset();
-    }
-    // After flipping i at iteration t: i becomes tabu for t+1..t+tau; the flip
-    // of iteration t-tau leaves the list unless repeated since.
-    __device__ __forceinline__ void tabu_push(const Sel &s) {
-        if (tau == 0) return;
-        int old = -1;
-#pragma unroll
-        for (int q = 0; q < TAU_MAX; ++q)
-            if (q == tau - 1) old = ring[q];
-#pragma unroll
-        for (int q = TAU_MAX - 1; q > 0; --q) ring[q] = ring[q - 1];
-        ring[0] = s.i;
-        set_lane_elem(pen, s.j, s.L, PEN);
-        if (old >= 0) {
-            bool again = false;
-#pragma unroll
-            for (int q = 0; q < TAU_MAX; ++q)
-                if (q < tau && ring[q] == old) again = true;
-            if (!again) set_lane_elem(pen, lidx_of(old), lidx_to_lane(old), 0);
-        }
+
+    // Non-tabu argmin of iteration t, or the plain argmin when every bit is tabu.
+    __device__ __forceinline__ Sel dom_argmin(int t) {
+        const int km = lane_min_dom(t);
+        const int m = wave_min(km >> LOGV);
+        return empty_dom(m) ? argmin_from(kminU, mU) : argmin_from(km, m);
     }
 
     // ------------------------------------------------------------- rules
@@ -323,8 +348,7 @@ struct Walker {
     __device__ __forceinline__ int phase_greedy(int cap) {
         if (cap <= 0) cap = 64 * n;                   // documented default bound
         int f = 0;
-        while (true) {
-            if ((mU >> SB) >= 0 || f >= cap) break;
+        while ((mU >> SB) < 0 && f < cap) {
             flip(argmin_from(kminU, mU));
             f++;
         }
@@ -333,7 +357,6 @@ struct Walker {
 
     // Straight (Section III-A.2): argmin over bits differing from the target.
     __device__ __forceinline__ int phase_straight(const uint64_t *target_bits) {
-        // target bits of this lane, then pen = PEN where x == d
         const int nw = (n + 63) / 64;
         uint64_t db = 0;
 #pragma unroll
@@ -341,48 +364,47 @@ struct Walker {
             const int k0 = s * SPAN + lane * V;
             const int w = k0 >> 6;
             const uint64_t word = w < nw ? target_bits[w] : 0ull;
-            uint64_t f = (word >> (k0 & 63)) & ((1ull << V) - 1);
-            f &= vb >> (s * V);                              // bits >= n are ignored
+            const uint64_t f = ((word >> (k0 & 63)) & ((1ull << V) - 1)) & (vb >> (s * V));   // bits >= n ignored
             db |= f << (s * V);
         }
-        const uint64_t diff = (xb ^ db);
+        const uint64_t diff = xb ^ db;
         int hd = 0;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s)
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const bool dif = (diff >> (s * V + e)) & 1;
-                pen[s * V + e] = dif ? 0 : PEN;
-                hd += dif;
-            }
+        for (int j = 0; j < EPL; ++j) {
+            const bool dif = (diff >> j) & 1;
+            ex[j] = dif ? EX_NEVER : EX_ALWAYS;
+            hd += dif;
+        }
         hd = (int)wave_sum64(hd);
+        kminM = lane_min_dom(0);
+        mM = wave_min(kminM >> LOGV);
         int f = 0;
         for (; f < hd; ++f) {
-            const Sel s = wave_argmin(lane_min_key_pen());
-            set_lane_elem(pen, s.j, s.L, PEN);
-            flip(s);
+            const Sel s = uniform(argmin_from(kminM, mM));
+            set_lane_elem(ex, s.j, s.L, EX_ALWAYS);
+            flip_dom(s, 0);
         }
-        pen_reset();
+        ex_reset();
         return f;
     }
 
     // Tabu greedy: T iterations of the non-tabu argmin.
-    __device__ __forceinline__ int phase_tabu_greedy(int T, int tau_) {
-        tabu_reset(tau_);
+    // The tabu mark of iteration t is set before the flip, so the refresh
+    // after it reduces the domain of iteration t + 1 together with Step 1.
+    __device__ __forceinline__ int phase_tabu_greedy(int T, int tau) {
+        kminM = kminU;            // iteration 1: nothing is tabu
+        mM = mU;
         for (int t = 1; t <= T; ++t) {
-            const int km = lane_min_key_pen();
-            const int m = wave_min(km >> LOGV);
-            const Sel s = (m >> SB) >= H_PAD ? argmin_from(kminU, mU) : argmin_from(km, m);
-            flip(s);
-            tabu_push(s);
+            const Sel s = dom_sel();
+            mark_tabu(s, t, tau);
+            flip_dom(s, t + 1);
         }
-        tabu_reset(0);
+        ex_reset();
         return T;
     }
 
     // CyclicMin (Section III-A.4): argmin over a sliding cyclic window.
-    __device__ __forceinline__ int phase_cyclicmin(int T, int tau_) {
-        tabu_reset(tau_);
+    __device__ __forceinline__ int phase_cyclicmin(int T, int tau) {
         int pos = 0;
         for (int t = 1; t <= T; ++t) {
             int w;
@@ -402,36 +424,27 @@ struct Walker {
             for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
+                    const int j = s * V + e;
                     const uint32_t off = (uint32_t)(gidx(s, e) - lo);
                     const bool in = wrap ? (off >= span) : (off < span);
-                    const int k = key[s * V + e];
-                    km = min(km, in ? k + pen[s * V + e] : KEY_BIG);
-                    kw = min(kw, in ? k : KEY_BIG);
+                    km = min(km, in && ex[j] < t ? key[j] : KEY_BIG);
+                    kw = min(kw, in ? key[j] : KEY_BIG);
                 }
-            int m = wave_min(km >> LOGV);
-            Sel s;
-            if ((m >> SB) >= H_PAD) s = wave_argmin(kw);
-            else s = argmin_from(km, m);
+            const int m = wave_min(km >> LOGV);
+            const Sel s = empty_dom(m) ? wave_argmin(kw) : argmin_from(km, m);
             flip(s);
-            tabu_push(s);
+            mark_tabu(s, t, tau);
             pos = (pos + w) % n;
         }
-        tabu_reset(0);
+        ex_reset();
         return T;
     }
 
-    // Least non-tabu key per lane, or the unmasked one when every bit is tabu.
-    __device__ __forceinline__ void domain(int &km, int &mm, bool &use_pen) {
-        km = lane_min_key_pen();
-        mm = wave_min(km >> LOGV);
-        use_pen = (mm >> SB) < H_PAD;
-        if (!use_pen) { km = kminU; mm = mU; }
-    }
-
-    // Candidates: elements whose key (+ penalty) is <= dk.  Counts them, draws
-    // r = floor(v * count / 2^32) and returns the r-th candidate (0-based, in
-    // increasing bit index: slot, then lane, then sub-index).
-    __device__ __forceinline__ Sel pick_rth(int dk, bool use_pen, uint32_t v) {
+    // Candidates: elements of the domain (ex < thr) whose key is <= dk.
+    // Counts them, draws r = floor(v * count / 2^32) and returns the r-th
+    // candidate (0-based, in increasing bit index: slot, then lane, then
+    // sub-index).
+    __device__ __forceinline__ Sel pick_rth(int dk, int thr, uint32_t v) {
         uint32_t cs[SLOTS];
         uint32_t c = 0;
 #pragma unroll
@@ -439,8 +452,8 @@ struct Walker {
             cs[s] = 0;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                const int k = key[s * V + e] + (use_pen ? pen[s * V + e] : 0);
-                cs[s] += (uint32_t)__builtin_popcountll(ballot(k <= dk));
+                const int j = s * V + e;
+                cs[s] += (uint32_t)__builtin_popcountll(ballot(key[j] <= dk && ex[j] < thr));
             }
             c += cs[s];
         }
@@ -465,8 +478,8 @@ struct Walker {
             uint32_t excl = 0;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                const int k = key[ss * V + e] + (use_pen ? pen[ss * V + e] : 0);
-                cm[e] = ballot(k <= dk);
+                const int j = ss * V + e;
+                cm[e] = ballot(key[j] <= dk && ex[j] < thr);
                 cnt += __builtin_amdgcn_inverse_ballot_w64(cm[e]) ? 1 : 0;
                 excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm[e] >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)cm[e], excl));
@@ -487,74 +500,66 @@ struct Walker {
             out.j = ss * V + e_sel;
             out.i = ss * SPAN + L * V + e_sel;
         });
-        out.d = readlane(get_key(out.j), out.L) >> KB;
+        out.d = readlane(key[out.j], out.L) >> KB;
         return out;
     }
 
+    // Domain threshold of iteration t: non-tabu bits, or every valid bit when
+    // all are tabu (R11); also returns the domain's least key.
+    __device__ __forceinline__ int domain(int t, int &km, int &mm) {
+        km = lane_min_dom(t);
+        mm = wave_min(km >> LOGV);
+        if (!empty_dom(mm)) return t;
+        km = kminU;
+        mm = mU;
+        return EX_ALWAYS;
+    }
+
     // MaxMin (Section III-A.3).
-    __device__ __forceinline__ int phase_maxmin(int T, int tau_, uint32_t ph) {
-        tabu_reset(tau_);
+    __device__ __forceinline__ int phase_maxmin(int T, int tau, uint32_t ph) {
         for (int t = 1; t <= T; ++t) {
             int km, mm;
-            bool use_pen;
-            domain(km, mm, use_pen);
+            const int thr = domain(t, km, mm);
             const int mind = mm >> SB;
-            // max delta over the domain (padding and tabu excluded)
             int kx = -KEY_BIG;
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s)
-#pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    // padding carries PEN permanently; tabu bits carry it while tabu
-                    const bool valid = (vb >> (s * V + e)) & 1;
-                    const int k = use_pen ? key[s * V + e] - pen[s * V + e]
-                                          : (valid ? key[s * V + e] : -KEY_BIG);
-                    kx = max(kx, k);
-                }
+            for (int j = 0; j < EPL; ++j) kx = max(kx, ex[j] < thr ? key[j] : -KEY_BIG);
             const int maxd = wave_max(kx) >> KB;
             const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
             const uint64_t g = ((uint64_t)(T - t) << 32) / (uint64_t)T;
             const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cube_frac(g)) >> 32;
             const int d = mind + (int)(((uint64_t)r.w[0] * (span + 1)) >> 32);
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
-            const Sel s = pick_rth(dk, use_pen, r.w[1]);
+            const Sel s = pick_rth(dk, thr, r.w[1]);
             flip(s);
-            tabu_push(s);
+            mark_tabu(s, t, tau);
         }
-        tabu_reset(0);
+        ex_reset();
         return T;
     }
 
     // PositiveMin (Section III-A.6).
-    __device__ __forceinline__ int phase_positivemin(int T, int tau_, uint32_t ph) {
-        tabu_reset(tau_);
+    __device__ __forceinline__ int phase_positivemin(int T, int tau, uint32_t ph) {
         for (int t = 1; t <= T; ++t) {
             int km, mm;
-            bool use_pen;
-            domain(km, mm, use_pen);
+            const int thr = domain(t, km, mm);
             int kp = KEY_BIG;
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s)
-#pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    const int k = key[s * V + e] + (use_pen ? pen[s * V + e] : 0);
-                    kp = min(kp, k >= (1 << KB) ? k : KEY_BIG);
-                }
+            for (int j = 0; j < EPL; ++j) kp = min(kp, (ex[j] < thr && key[j] >= (1 << KB)) ? key[j] : KEY_BIG);
             const int pd = wave_min(kp >> LOGV) >> SB;
             const int d = pd >= H_PAD ? H_PAD - 1 : pd;
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
             const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_POSMIN << 24, seed);
-            const Sel s = pick_rth(dk, use_pen, r.w[0]);
+            const Sel s = pick_rth(dk, thr, r.w[0]);
             flip(s);
-            tabu_push(s);
+            mark_tabu(s, t, tau);
         }
-        tabu_reset(0);
+        ex_reset();
         return T;
     }
 
     // RandomMin (Section III-A.5): candidates by random byte < q(t).
-    __device__ __forceinline__ int phase_randommin(int T, int tau_, uint32_t ph) {
-        tabu_reset(tau_);
+    __device__ __forceinline__ int phase_randommin(int T, int tau, uint32_t ph) {
         for (int t = 1; t <= T; ++t) {
             int q;
             if (t >= T) {
@@ -576,26 +581,18 @@ struct Walker {
                 const uint32_t wb = w0 == 0 ? r.w[1] : (w0 == 1 ? r.w[2] : r.w[3]);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
+                    const int j = s * V + e;
                     const uint32_t word = e < 4 ? wa : wb;
                     const int byte = (int)((word >> (8 * (e & 3))) & 0xFFu);
-                    const int k = key[s * V + e] + pen[s * V + e];
-                    kr = min(kr, byte < q ? k : KEY_BIG);
+                    kr = min(kr, (byte < q && ex[j] < t) ? key[j] : KEY_BIG);
                 }
             }
             const int m = wave_min(kr >> LOGV);
-            Sel s;
-            if ((m >> SB) < H_PAD) {
-                s = argmin_from(kr, m);
-            } else {
-                int km, mm;
-                bool use_pen;
-                domain(km, mm, use_pen);
-                s = argmin_from(km, mm);
-            }
+            const Sel s = empty_dom(m) ? dom_argmin(t) : argmin_from(kr, m);
             flip(s);
-            tabu_push(s);
+            mark_tabu(s, t, tau);
         }
-        tabu_reset(0);
+        ex_reset();
         return T;
     }
 
@@ -609,22 +606,25 @@ struct Walker {
         return 2 * n - 1;
     }
 
-    __device__ __forceinline__ int run_phase(int rule, int T, int tau_, uint32_t ph, const uint64_t *target_bits, int cap) {
+    __device__ __forceinline__ int run_phase(int rule, int T, int tau, uint32_t ph, const uint64_t *target_bits,
+                                             int cap) {
+        tau = tau < 0 ? 0 : (tau > TAU_MAX ? TAU_MAX : tau);
         switch (rule) {
         case GREEDY: return phase_greedy(cap);
         case STRAIGHT: return phase_straight(target_bits);
-        case MAXMIN: return phase_maxmin(T, tau_, ph);
-        case CYCLICMIN: return phase_cyclicmin(T, tau_);
-        case RANDOMMIN: return phase_randommin(T, tau_, ph);
-        case POSITIVEMIN: return phase_positivemin(T, tau_, ph);
+        case MAXMIN: return phase_maxmin(T, tau, ph);
+        case CYCLICMIN: return phase_cyclicmin(T, tau);
+        case RANDOMMIN: return phase_randommin(T, tau, ph);
+        case POSITIVEMIN: return phase_positivemin(T, tau, ph);
         case TWONEIGHBOR: return phase_twoneighbor();
-        case TABU_GREEDY: return phase_tabu_greedy(T, tau_);
+        case TABU_GREEDY: return phase_tabu_greedy(T, tau);
         default: return 0;
         }
     }
 
     // Batch search (Section III-B): Straight -> Greedy -> {main -> Greedy}*.
-    __device__ __forceinline__ int batch(const uint64_t *target_bits, int rule, int T, int Bn, int tau_, uint32_t &ph, int cap) {
+    __device__ __forceinline__ int batch(const uint64_t *target_bits, int rule, int T, int Bn, int tau, uint32_t &ph,
+                                         int cap) {
         bb = xb;
         Eb = E;
         note_best();
@@ -632,7 +632,7 @@ struct Walker {
         int f = phase_straight(target_bits);
         f += phase_greedy(cap);
         while (f < Bn) {
-            const int fm = run_phase(rule, T, tau_, ph, nullptr, cap);
+            const int fm = run_phase(rule, T, tau, ph, nullptr, cap);
             if (fm <= 0) break;                       // not a main algorithm: stop
             f += fm;
             ph++;
