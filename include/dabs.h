@@ -238,6 +238,42 @@ int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream);
  */
 int dabs_solver_timing(dabs_solver *s, double *out_host, int32_t reset);
 
+/*
+ * Batched solver: many problems of uneven n served by one device loop.  Every
+ * round draws the targets of all instances of all problems, runs their batch
+ * searches with persistent work-queue kernels (one per weight type and slot
+ * count, on parallel streams, longest problems first), inserts the packets
+ * into each problem's pools and advances the round.  Each problem has its
+ * own parameters, pools, instances and generator key (params[p].seed), and
+ * evolves exactly as dabs_solver_* on that problem alone would.
+ *   probs[p], params[p], instances[p]  for p < nprob (the problems must
+ *   outlive the batch).
+ */
+typedef struct dabs_batched dabs_batched;
+int dabs_batched_create(dabs_problem *const *probs, int32_t nprob, const dabs_ga_params *params,
+                        const int32_t *instances, void *stream, dabs_batched **out);
+int dabs_batched_destroy(dabs_batched *b);
+/*
+ * Run `rounds` rounds.  use_graph != 0 captures one round into a HIP graph
+ * on first use and replays it (ignored when the batch times its kernels).
+ * target_e_dev: nullable [nprob] int64 time-to-target energies; the first
+ * hit of each problem is recorded in 100 MHz device ticks from the start of
+ * this call.
+ */
+int dabs_batched_run(dabs_batched *b, int32_t rounds, const int64_t *target_e_dev, int32_t use_graph,
+                     void *stream);
+/* [nprob][2] int64: first-hit ticks (-1 if not reached) and best pooled energy. */
+int dabs_batched_progress(const dabs_batched *b, int64_t *out_dev, void *stream);
+/* Pools / instance state of problem `prob`, as dabs_solver_pools / _state. */
+int dabs_batched_pools(const dabs_batched *b, int32_t prob, uint64_t *bits_dev, int64_t *e_dev,
+                       int32_t *algo_dev, int32_t *op_dev, void *stream);
+int dabs_batched_state(const dabs_batched *b, int32_t prob, uint64_t *x_dev, int64_t *e_dev,
+                       uint32_t *phase_dev, void *stream);
+/* Total flips of all instances of all problems so far (one int64). */
+int dabs_batched_flips(const dabs_batched *b, int64_t *total_flips_dev, void *stream);
+/* As dabs_solver_timing (DABS_SOLVER_TIME_WALK in any problem's flags). */
+int dabs_batched_timing(dabs_batched *b, double *out_host, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,14 @@ _SIGS = {
     "dabs_solver_state": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "dabs_solver_progress": ([_P, _P, _P], C.c_int),
     "dabs_solver_timing": ([_P, C.POINTER(C.c_double), C.c_int32], C.c_int),
+    "dabs_batched_create": ([_P, C.c_int32, _P, _P, _P, C.POINTER(_P)], C.c_int),
+    "dabs_batched_destroy": ([_P], C.c_int),
+    "dabs_batched_run": ([_P, C.c_int32, _P, C.c_int32, _P], C.c_int),
+    "dabs_batched_progress": ([_P, _P, _P], C.c_int),
+    "dabs_batched_pools": ([_P, C.c_int32, _P, _P, _P, _P, _P], C.c_int),
+    "dabs_batched_state": ([_P, C.c_int32, _P, _P, _P, _P], C.c_int),
+    "dabs_batched_flips": ([_P, _P, _P], C.c_int),
+    "dabs_batched_timing": ([_P, C.POINTER(C.c_double), C.c_int32], C.c_int),
 }
 
 _lib = None
@@ -243,4 +251,57 @@ def dabs_solver_timing(s: Solver, reset: bool = False):
     """(walk milliseconds, walk launches, flips) since the last reset."""
     out = (C.c_double * 3)()
     _check(lib().dabs_solver_timing(s.handle, out, int(reset)))
+    return out[0], int(out[1]), int(out[2])
+
+
+class Batched:
+    def __init__(self, handle, problems, params, instances):
+        self.handle, self.problems, self.params, self.instances = handle, problems, params, instances
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.dabs_batched_destroy(h)
+
+
+def dabs_batched_create(problems, params, instances, stream=None) -> Batched:
+    """problems: list of Problem; params: list of dabs_ga_params; instances: list of int."""
+    n = len(problems)
+    hp = (C.c_void_p * n)(*[p.handle.value if isinstance(p.handle, C.c_void_p) else p.handle for p in problems])
+    gp = (dabs_ga_params * n)(*params)
+    ip = (C.c_int32 * n)(*instances)
+    h = C.c_void_p()
+    _check(lib().dabs_batched_create(hp, n, gp, ip, _stream(stream), C.byref(h)))
+    return Batched(h, list(problems), list(params), list(instances))
+
+
+def dabs_batched_destroy(b: Batched):
+    h, b.handle = b.handle, None
+    if h:
+        _check(lib().dabs_batched_destroy(h))
+
+
+def dabs_batched_run(b: Batched, rounds: int, target_e=None, use_graph: bool = True, stream=None):
+    _check(lib().dabs_batched_run(b.handle, rounds, _ptr(target_e), int(use_graph), _stream(stream)))
+
+
+def dabs_batched_progress(b: Batched, out, stream=None):
+    _check(lib().dabs_batched_progress(b.handle, _ptr(out), _stream(stream)))
+
+
+def dabs_batched_pools(b: Batched, prob: int, bits=None, e=None, algo=None, op=None, stream=None):
+    _check(lib().dabs_batched_pools(b.handle, prob, _ptr(bits), _ptr(e), _ptr(algo), _ptr(op), _stream(stream)))
+
+
+def dabs_batched_state(b: Batched, prob: int, x=None, e=None, phase=None, stream=None):
+    _check(lib().dabs_batched_state(b.handle, prob, _ptr(x), _ptr(e), _ptr(phase), _stream(stream)))
+
+
+def dabs_batched_flips(b: Batched, out, stream=None):
+    _check(lib().dabs_batched_flips(b.handle, _ptr(out), _stream(stream)))
+
+
+def dabs_batched_timing(b: Batched, reset: bool = False):
+    out = (C.c_double * 3)()
+    _check(lib().dabs_batched_timing(b.handle, out, int(reset)))
     return out[0], int(out[1]), int(out[2])

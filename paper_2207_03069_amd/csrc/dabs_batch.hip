@@ -1,0 +1,654 @@
+// dabs_batch.hip -- the genetic algorithm of Section IV on device-resident
+// solution pools, for one problem (dabs_solver_*) or many problems of uneven
+// size in one batch (dabs_batched_*).  A round is: target generation for
+// every instance (adaptive operation / algorithm choice, rank selection,
+// genetic operation), one batch search per instance by persistent work-queue
+// kernels (one per slot class, on parallel streams), packet insertion into
+// the pools in instance order, round counter increment.  A batch can capture
+// its round once into a HIP graph and replay it.
+#include <algorithm>
+#include <string.h>
+#include <vector>
+
+#include "dabs_device.h"
+#include "dabs_internal.h"
+
+using namespace dabs;
+
+#define HIP_OK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return dabs_fail(DABS_E_HIP, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+namespace dabs {
+
+enum { KIND_CHOICE = 0, KIND_BITS = 2, KIND_MASK = 3, KIND_RANDVEC = 4 };
+constexpr int POOL_MAX = 1024;
+constexpr int MAX_CLASSES = 8;
+
+__device__ __forceinline__ uint64_t tail_mask(int n, int w) {
+    const int rem = n - 64 * w;
+    return rem >= 64 ? ~0ull : (rem <= 0 ? 0ull : ((1ull << rem) - 1));
+}
+
+// 64 bits of a random vector: word w is half of the 128-bit chunk w/2 of the
+// draw (a, b, chunk, tag).
+__device__ __forceinline__ uint64_t rand_word(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag, int w) {
+    const R4 r = philox(a, b, (uint32_t)(w >> 1), tag, seed);
+    return (w & 1) ? ((uint64_t)r.w[3] << 32 | r.w[2]) : ((uint64_t)r.w[1] << 32 | r.w[0]);
+}
+
+// Bits of word w whose per-bit u32 draw is below p (one draw per bit).
+__device__ __forceinline__ uint64_t thresh_word(uint64_t seed, uint32_t round, uint32_t inst, int w, uint32_t p) {
+    uint64_t m = 0;
+    for (int c = 0; c < 16; ++c) {
+        const R4 r = philox(round, inst, (uint32_t)(w * 16 + c), ((uint32_t)TAG_GA << 24) | KIND_BITS, seed);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (r.w[q] < p) m |= 1ull << (c * 4 + q);
+    }
+    return m;
+}
+
+// bits [lo, hi) of word w
+__device__ __forceinline__ uint64_t range_word(int lo, int hi, int w) {
+    const int b0 = 64 * w;
+    const int s = lo - b0 < 0 ? 0 : (lo - b0 > 64 ? 64 : lo - b0);
+    const int e = hi - b0 < 0 ? 0 : (hi - b0 > 64 ? 64 : hi - b0);
+    const uint64_t upto_e = e >= 64 ? ~0ull : ((1ull << e) - 1);
+    const uint64_t upto_s = s >= 64 ? ~0ull : ((1ull << s) - 1);
+    return upto_e & ~upto_s;
+}
+
+__device__ __forceinline__ uint32_t rank_index(uint32_t u, uint32_t m) { return scale32((uint32_t)cube_frac(u), m); }
+
+// Section IV-A: pools start with random vectors, energy +inf and random
+// algorithm / operation columns.  One thread per (pool, entry, word) of one
+// problem.
+__global__ void k_pool_init(BatchDev b, int p) {
+    const ProbDesc d = b.desc[p];
+    const int P = d.g.npools, m = d.g.capacity, nw = d.nw;
+    const int64_t total = (int64_t)P * m * nw;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int w = (int)(t % nw);
+        const int r = (int)((t / nw) % m);
+        const int q = (int)(t / ((int64_t)nw * m));
+        b.pool_bits[d.pool_word0 + t] =
+            rand_word(d.g.seed, (uint32_t)r, (uint32_t)q, ((uint32_t)TAG_POOL << 24) | 1u, w) & tail_mask(d.n, w);
+        if (w == 0) {
+            const R4 dr = philox((uint32_t)r, (uint32_t)q, 0, (uint32_t)TAG_POOL << 24, d.g.seed);
+            const int64_t cell = d.pool_cell0 + (int64_t)q * m + r;
+            b.pool_e[cell] = E_INF;
+            b.pool_algo[cell] = d.g.algos[scale32(dr.w[0], (uint32_t)d.g.n_algos)];
+            b.pool_op[cell] = d.g.ops[scale32(dr.w[1], (uint32_t)d.g.n_ops)];
+        }
+    }
+}
+
+// Target generation (Section IV-A, IV-B): one wave per global instance, lane
+// w builds word w of the target (n <= 4096: at most 64 words).
+__global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
+    const int gi = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (gi >= total) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int p = __builtin_amdgcn_readfirstlane(b.inst_prob[gi]);
+    const ProbDesc &d = b.desc[p];
+    const dabs_ga_params &g = d.g;
+    const int inst = gi - d.inst0;
+    const int m = g.capacity, n = d.n, nw = d.nw, P = g.npools;
+    const int q = inst % P;
+    const uint32_t rd = (uint32_t)b.ctr[2];
+    const R4 c = philox(rd, (uint32_t)inst, 0, ((uint32_t)TAG_GA << 24) | KIND_CHOICE, g.seed);
+    const R4 v = philox(rd, (uint32_t)inst, 1, ((uint32_t)TAG_GA << 24) | KIND_CHOICE, g.seed);
+    const int64_t cell = d.pool_cell0 + (int64_t)q * m;
+    const int op = c.w[0] < g.p_explore ? g.ops[scale32(c.w[1], (uint32_t)g.n_ops)]
+                                        : b.pool_op[cell + scale32(c.w[1], (uint32_t)m)];
+    const int algo = c.w[2] < g.p_explore ? g.algos[scale32(c.w[3], (uint32_t)g.n_algos)]
+                                          : b.pool_algo[cell + scale32(c.w[3], (uint32_t)m)];
+    const int qb = op == DABS_OP_XROSSOVER ? (q + 1) % P : q;
+    const uint64_t *pool = b.pool_bits + d.pool_word0;
+    const uint64_t *pa = pool + ((int64_t)q * m + rank_index(v.w[0], (uint32_t)m)) * nw;
+    const uint64_t *pb = pool + ((int64_t)qb * m + rank_index(v.w[1], (uint32_t)m)) * nw;
+    const uint64_t *p0 = pool + (int64_t)q * m * nw;
+    uint64_t *out = b.target + d.inst_word0 + (int64_t)inst * nw;
+    const uint32_t lo32 = (uint32_t)(n < 32 ? n : 32);
+    const uint32_t hi32 = (uint32_t)(n / 2) > lo32 ? (uint32_t)(n / 2) : lo32;
+    for (int w = lane; w < nw; w += WAVE) {
+        const uint64_t A = pa[w];
+        uint64_t t;
+        switch (op) {
+        case DABS_OP_RANDOM:
+            t = rand_word(g.seed, rd, (uint32_t)inst, ((uint32_t)TAG_GA << 24) | KIND_RANDVEC, w);
+            break;
+        case DABS_OP_BEST:
+            t = p0[w];
+            break;
+        case DABS_OP_MUTATION:
+            t = A ^ thresh_word(g.seed, rd, (uint32_t)inst, w, g.p_mutation);
+            break;
+        case DABS_OP_CROSSOVER:
+        case DABS_OP_XROSSOVER: {
+            uint64_t sel;
+            if (g.crossover_kind == 1) {
+                const uint32_t x1 = scale32(v.w[2], (uint32_t)n + 1), x2 = scale32(v.w[3], (uint32_t)n + 1);
+                sel = range_word((int)(x1 < x2 ? x1 : x2), (int)(x1 < x2 ? x2 : x1), w);
+            } else {
+                sel = rand_word(g.seed, rd, (uint32_t)inst, ((uint32_t)TAG_GA << 24) | KIND_MASK, w);
+            }
+            t = (A & ~sel) | (pb[w] & sel);
+            break;
+        }
+        case DABS_OP_ZERO:
+            t = A & ~thresh_word(g.seed, rd, (uint32_t)inst, w, g.p_zero);
+            break;
+        case DABS_OP_ONE:
+            t = A | thresh_word(g.seed, rd, (uint32_t)inst, w, g.p_one);
+            break;
+        case DABS_OP_INTERVALZERO: {
+            // zero positions st .. st+len-1 (mod n)
+            const uint32_t len = lo32 + scale32(v.w[2], hi32 - lo32 + 1);
+            const int st = (int)scale32(v.w[3], (uint32_t)n);
+            const int end = st + (int)len;
+            uint64_t z = range_word(st, end < n ? end : n, w);
+            if (end > n) z |= range_word(0, end - n, w);
+            t = A & ~z;
+            break;
+        }
+        default:
+            t = A;
+            break;
+        }
+        out[w] = t & tail_mask(n, w);
+    }
+    if (lane == 0) {
+        b.algo[gi] = algo;
+        b.op[gi] = op;
+    }
+}
+
+// Packet insertion (Section III-C, IV): one wave per (problem, pool), the
+// pool's instances in increasing order; insert only when strictly better
+// than the worst entry and no identical vector is pooled; ascending energies,
+// a newcomer after equal energies.  The energy / algorithm / operation
+// columns are worked on in LDS; each lane moves only its own words.
+__global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pools) {
+    __shared__ long long se[POOL_MAX];
+    __shared__ int sal[POOL_MAX], sop[POOL_MAX];
+    const int2 pq = pools[blockIdx.x];
+    const ProbDesc &d = b.desc[pq.x];
+    const int q = pq.y, P = d.g.npools, m = d.g.capacity, nw = d.nw;
+    const int lane = (int)threadIdx.x;
+    const int64_t cell = d.pool_cell0 + (int64_t)q * m;
+    int64_t *pe = b.pool_e + cell;
+    int32_t *pal = b.pool_algo + cell, *pop = b.pool_op + cell;
+    uint64_t *pbits = b.pool_bits + d.pool_word0 + (int64_t)q * m * nw;
+    for (int r = lane; r < m; r += WAVE) {
+        se[r] = pe[r];
+        sal[r] = pal[r];
+        sop[r] = pop[r];
+    }
+    __syncthreads();
+    for (int i = q; i < d.instances; i += P) {
+        const int64_t gi = d.inst0 + i;
+        const int64_t e = b.best_e[gi];
+        if (!(e < se[m - 1])) continue;
+        const uint64_t *bits = b.best + d.inst_word0 + (int64_t)i * nw;
+        bool dup = false;
+        for (int r = 0; r < m && !dup; ++r) {
+            bool diff = false;
+            for (int w = lane; w < nw; w += WAVE) diff |= pbits[(int64_t)r * nw + w] != bits[w];
+            dup = __builtin_amdgcn_ballot_w64(diff) == 0;
+        }
+        if (dup) continue;
+        int pos = 0;
+        while (pos < m && se[pos] <= e) ++pos;
+        for (int r = m - 1; r > pos; --r)
+            for (int w = lane; w < nw; w += WAVE) pbits[(int64_t)r * nw + w] = pbits[(int64_t)(r - 1) * nw + w];
+        for (int w = lane; w < nw; w += WAVE) pbits[(int64_t)pos * nw + w] = bits[w];
+        __syncthreads();
+        if (lane == 0) {
+            for (int r = m - 1; r > pos; --r) {
+                se[r] = se[r - 1];
+                sal[r] = sal[r - 1];
+                sop[r] = sop[r - 1];
+            }
+            se[pos] = e;
+            sal[pos] = b.algo[gi];
+            sop[pos] = b.op[gi];
+        }
+        __syncthreads();
+    }
+    for (int r = lane; r < m; r += WAVE) {
+        pe[r] = se[r];
+        pal[r] = sal[r];
+        pop[r] = sop[r];
+    }
+}
+
+// Start of a round: clear the work-queue heads (a kernel, not a memset, so
+// the round can be captured in a graph).
+__global__ void k_round_begin(unsigned long long *ctr, int nq) {
+    if ((int)threadIdx.x < nq) ctr[3 + threadIdx.x] = 0;
+}
+
+__global__ void k_round_end(unsigned long long *ctr) {
+    if (threadIdx.x == 0) ctr[2] += 1;
+}
+
+// Start of a run: clock, and per-problem targets and first-hit records.
+__global__ void k_run_begin(BatchDev b, int nprob, const int64_t *target_e) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) b.ctr[1] = __builtin_amdgcn_s_memrealtime();
+    if (p < nprob) {
+        b.desc[p].target_e = target_e ? target_e[p] : INT64_MIN;
+        b.desc[p].hit = ~0ull;
+    }
+}
+
+// per problem: [first-hit ticks or -1, best pooled energy]
+__global__ void k_progress(BatchDev b, int nprob, int64_t *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    const ProbDesc &d = b.desc[p];
+    int64_t best = E_INF;
+    for (int q = 0; q < d.g.npools; ++q) {
+        const int64_t e = b.pool_e[d.pool_cell0 + (int64_t)q * d.g.capacity];
+        best = e < best ? e : best;
+    }
+    out[2 * p] = d.hit == ~0ull ? -1 : (int64_t)d.hit;
+    out[2 * p + 1] = best;
+}
+
+}  // namespace dabs
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct dabs_batched {
+    int nprob;
+    std::vector<ProbDesc> hdesc;
+    int64_t total_inst, pool_cells, pool_words, inst_words;
+    BatchDev d;
+    int2 *items;                       // device, grouped by class
+    int2 *pool_list;                   // device, (problem, pool)
+    int npool_list;
+    struct Cls { int wtype, slots, begin, count; };
+    std::vector<Cls> classes;
+    hipStream_t side[MAX_CLASSES];
+    hipEvent_t fork, join[MAX_CLASSES];
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool graph_ready;
+    int ttt;                           // time-to-target armed for the captured round
+    // optional timing of the batch-search kernels (DABS_SOLVER_TIME_WALK)
+    bool timed;
+    static constexpr int NEV = 256;
+    hipEvent_t ev[2 * NEV];
+    int nev;
+    double walk_ms;
+    long long walk_launches, flips_at_reset;
+};
+
+static void batched_free(dabs_batched *s) {
+    if (s->graph_ready) {
+        (void)hipGraphExecDestroy(s->exec);
+        (void)hipGraphDestroy(s->graph);
+    }
+    for (int i = 0; i < MAX_CLASSES; ++i) {
+        if (s->side[i]) (void)hipStreamDestroy(s->side[i]);
+        if (s->join[i]) (void)hipEventDestroy(s->join[i]);
+    }
+    if (s->fork) (void)hipEventDestroy(s->fork);
+    for (int i = 0; i < 2 * dabs_batched::NEV; ++i)
+        if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+    void *ptrs[] = {s->d.desc, s->d.pool_bits, s->d.pool_e, s->d.pool_algo, s->d.pool_op, s->d.x, s->d.target,
+                    s->d.best, s->d.e, s->d.best_e, s->d.ph, s->d.algo, s->d.op, s->d.inst_prob, s->d.ctr,
+                    s->items, s->pool_list};
+    for (void *q : ptrs) (void)hipFree(q);
+    delete s;
+}
+
+static int check_params(const dabs_problem *p, const dabs_ga_params *g, int instances) {
+    if (!p || !g) return dabs_fail(DABS_E_INVALID, "null problem or params");
+    if (instances < 1) return dabs_fail(DABS_E_INVALID, "instances must be >= 1");
+    if (g->npools < 1 || g->capacity < 1 || g->capacity > POOL_MAX) return dabs_fail(DABS_E_INVALID, "bad pools");
+    if (g->n_algos < 1 || g->n_algos > 8 || g->n_ops < 1 || g->n_ops > 16)
+        return dabs_fail(DABS_E_INVALID, "bad algorithm / operation lists");
+    for (int i = 0; i < g->n_algos; ++i)
+        if (g->algos[i] < DABS_MAXMIN || g->algos[i] > DABS_TWONEIGHBOR)
+            return dabs_fail(DABS_E_INVALID, "algorithm %d is not a main search algorithm", g->algos[i]);
+    for (int i = 0; i < g->n_ops; ++i)
+        if (g->ops[i] < DABS_OP_RANDOM || g->ops[i] > DABS_OP_INTERVALZERO)
+            return dabs_fail(DABS_E_INVALID, "bad genetic operation %d", g->ops[i]);
+    if (g->T < 1 || g->Bn < 0 || g->tau < 0 || g->tau > TAU_MAX) return dabs_fail(DABS_E_INVALID, "bad T / Bn / tau");
+    if (g->crossover_kind != 0 && g->crossover_kind != 1) return dabs_fail(DABS_E_INVALID, "bad crossover kind");
+    return DABS_OK;
+}
+
+static int batched_create(const dabs_problem *const *probs, int nprob, const dabs_ga_params *params,
+                          const int32_t *instances, uint32_t flags, hipStream_t st, dabs_batched **out) {
+    if (!probs || !params || !instances || !out || nprob < 1) return dabs_fail(DABS_E_INVALID, "bad batch arguments");
+    for (int p = 0; p < nprob; ++p) {
+        const int c = check_params(probs[p], &params[p], instances[p]);
+        if (c != DABS_OK) return c;
+    }
+    dabs_batched *s = new dabs_batched();
+    s->nprob = nprob;
+    s->hdesc.resize(nprob);
+    int64_t inst = 0, cells = 0, pwords = 0, iwords = 0;
+    for (int p = 0; p < nprob; ++p) {
+        ProbDesc &d = s->hdesc[p];
+        memset(&d, 0, sizeof(d));
+        const dabs_problem *pr = probs[p];
+        d.W = pr->W; d.diag = pr->diag; d.ld = pr->ld; d.n = pr->n; d.nw = (pr->n + 63) / 64;
+        d.wtype = pr->wtype; d.slots = walk_slots(pr->wtype, pr->n);
+        d.instances = instances[p]; d.inst0 = (int32_t)inst;
+        d.g = params[p];
+        d.pool_cell0 = cells; d.pool_word0 = pwords; d.inst_word0 = iwords;
+        d.target_e = INT64_MIN; d.hit = ~0ull;
+        const int64_t pc = (int64_t)d.g.npools * d.g.capacity;
+        inst += d.instances; cells += pc; pwords += pc * d.nw; iwords += (int64_t)d.instances * d.nw;
+    }
+    s->total_inst = inst; s->pool_cells = cells; s->pool_words = pwords; s->inst_words = iwords;
+    // items grouped by (wtype, slots), longest first inside a class
+    std::vector<int2> items;
+    std::vector<std::pair<int, int>> keys;
+    for (int p = 0; p < nprob; ++p) keys.push_back({s->hdesc[p].wtype, s->hdesc[p].slots});
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    if ((int)keys.size() > MAX_CLASSES) {
+        delete s;
+        return dabs_fail(DABS_E_UNSUPPORTED, "too many size classes");
+    }
+    for (auto &k : keys) {
+        std::vector<int> ps;
+        for (int p = 0; p < nprob; ++p)
+            if (s->hdesc[p].wtype == k.first && s->hdesc[p].slots == k.second) ps.push_back(p);
+        std::stable_sort(ps.begin(), ps.end(), [&](int a, int b) {
+            const ProbDesc &A = s->hdesc[a], &B = s->hdesc[b];
+            return (int64_t)A.n * (A.g.Bn + A.n) > (int64_t)B.n * (B.g.Bn + B.n);
+        });
+        dabs_batched::Cls c = {k.first, k.second, (int)items.size(), 0};
+        for (int p : ps)
+            for (int i = 0; i < s->hdesc[p].instances; ++i) items.push_back(make_int2(p, i));
+        c.count = (int)items.size() - c.begin;
+        s->classes.push_back(c);
+    }
+    std::vector<int2> pl;
+    for (int p = 0; p < nprob; ++p)
+        for (int q = 0; q < s->hdesc[p].g.npools; ++q) pl.push_back(make_int2(p, q));
+    s->npool_list = (int)pl.size();
+    std::vector<int32_t> ip(inst);
+    for (int p = 0; p < nprob; ++p)
+        for (int i = 0; i < s->hdesc[p].instances; ++i) ip[s->hdesc[p].inst0 + i] = p;
+    BatchDev &d = s->d;
+    bool ok = hipMalloc(&d.desc, sizeof(ProbDesc) * nprob) == hipSuccess &&
+              hipMalloc(&d.pool_bits, 8 * (size_t)pwords) == hipSuccess &&
+              hipMalloc(&d.pool_e, 8 * (size_t)cells) == hipSuccess &&
+              hipMalloc(&d.pool_algo, 4 * (size_t)cells) == hipSuccess &&
+              hipMalloc(&d.pool_op, 4 * (size_t)cells) == hipSuccess &&
+              hipMalloc(&d.x, 8 * (size_t)iwords) == hipSuccess && hipMalloc(&d.target, 8 * (size_t)iwords) == hipSuccess &&
+              hipMalloc(&d.best, 8 * (size_t)iwords) == hipSuccess && hipMalloc(&d.e, 8 * (size_t)inst) == hipSuccess &&
+              hipMalloc(&d.best_e, 8 * (size_t)inst) == hipSuccess && hipMalloc(&d.ph, 4 * (size_t)inst) == hipSuccess &&
+              hipMalloc(&d.algo, 4 * (size_t)inst) == hipSuccess && hipMalloc(&d.op, 4 * (size_t)inst) == hipSuccess &&
+              hipMalloc(&d.inst_prob, 4 * (size_t)inst) == hipSuccess &&
+              hipMalloc(&d.ctr, 8 * (3 + MAX_CLASSES)) == hipSuccess &&
+              hipMalloc(&s->items, sizeof(int2) * items.size()) == hipSuccess &&
+              hipMalloc(&s->pool_list, sizeof(int2) * pl.size()) == hipSuccess;
+    if (!ok) {
+        batched_free(s);
+        return dabs_fail(DABS_E_NOMEM, "batch allocation failed");
+    }
+    s->timed = (flags & DABS_SOLVER_TIME_WALK) != 0;
+    ok = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming) == hipSuccess;
+    for (size_t c = 0; c < s->classes.size() && ok; ++c)
+        ok = hipStreamCreateWithFlags(&s->side[c], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&s->join[c], hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < 2 * dabs_batched::NEV && ok && s->timed; ++i) ok = hipEventCreate(&s->ev[i]) == hipSuccess;
+    if (!ok) {
+        batched_free(s);
+        return dabs_fail(DABS_E_HIP, "stream / event creation failed");
+    }
+    // instances start at X = 0 with E = 0 (Section III-B)
+    ok = hipMemcpyAsync(d.desc, s->hdesc.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(s->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(s->pool_list, pl.data(), sizeof(int2) * pl.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(d.inst_prob, ip.data(), 4 * ip.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemsetAsync(d.x, 0, 8 * (size_t)iwords, st) == hipSuccess &&
+         hipMemsetAsync(d.e, 0, 8 * (size_t)inst, st) == hipSuccess &&
+         hipMemsetAsync(d.ph, 0, 4 * (size_t)inst, st) == hipSuccess &&
+         hipMemsetAsync(d.ctr, 0, 8 * (3 + MAX_CLASSES), st) == hipSuccess;
+    for (int p = 0; p < nprob && ok; ++p) {
+        const int64_t total = (int64_t)s->hdesc[p].g.npools * s->hdesc[p].g.capacity * s->hdesc[p].nw;
+        const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_pool_init, dim3(blocks), dim3(256), 0, st, d, p);
+        ok = hipGetLastError() == hipSuccess;
+    }
+    // the host vectors must outlive the asynchronous copies
+    if (!ok || hipStreamSynchronize(st) != hipSuccess) {
+        batched_free(s);
+        return dabs_fail(DABS_E_HIP, "batch initialisation failed");
+    }
+    *out = s;
+    return DABS_OK;
+}
+
+// One round on stream st: targets, batch searches (one persistent kernel per
+// size class; classes run on parallel streams), packet insertion, round++.
+static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturing) {
+    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, st, s->d.ctr, (int)s->classes.size());
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
+                       (int)s->total_inst);
+    HIP_OK(hipGetLastError());
+    const bool timed = s->timed && !capturing;
+    if (timed && s->nev == dabs_batched::NEV) {
+        double out[3];
+        const int r = dabs_batched_timing(s, out, 0);
+        if (r != DABS_OK) return r;
+    }
+    if (timed) HIP_OK(hipEventRecord(s->ev[2 * s->nev], st));
+    const int nc = (int)s->classes.size();
+    if (nc > 1) HIP_OK(hipEventRecord(s->fork, st));
+    for (int c = 0; c < nc; ++c) {
+        hipStream_t cs = nc > 1 ? s->side[c] : st;
+        if (nc > 1) HIP_OK(hipStreamWaitEvent(cs, s->fork, 0));
+        ItemsArgs a;
+        a.b = s->d;
+        a.items = s->items + s->classes[c].begin;
+        a.nitems = s->classes[c].count;
+        a.queue = (unsigned int *)(s->d.ctr + 3 + c);
+        a.ttt = ttt;
+        HIP_OK(launch_walk_items(s->classes[c].wtype, s->classes[c].slots, a, cs));
+        if (nc > 1) HIP_OK(hipEventRecord(s->join[c], cs));
+    }
+    for (int c = 0; c < nc && nc > 1; ++c) HIP_OK(hipStreamWaitEvent(st, s->join[c], 0));
+    if (timed) {
+        HIP_OK(hipEventRecord(s->ev[2 * s->nev + 1], st));
+        s->nev++;
+    }
+    hipLaunchKernelGGL(k_pool_insert, dim3(s->npool_list), dim3(64), 0, st, s->d, s->pool_list);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, st, s->d.ctr);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+static int batched_run(dabs_batched *s, int rounds, const int64_t *target_e, int use_graph, hipStream_t st) {
+    if (rounds < 0) return dabs_fail(DABS_E_INVALID, "rounds < 0");
+    const int ttt = target_e ? 1 : 0;
+    hipLaunchKernelGGL(k_run_begin, dim3((s->nprob + 255) / 256), dim3(256), 0, st, s->d, s->nprob, target_e);
+    HIP_OK(hipGetLastError());
+    if (!use_graph || s->timed) {
+        for (int r = 0; r < rounds; ++r) {
+            const int c = enqueue_round(s, st, ttt, false);
+            if (c != DABS_OK) return c;
+        }
+        return DABS_OK;
+    }
+    if (!s->graph_ready || s->ttt != ttt) {
+        if (s->graph_ready) {
+            (void)hipGraphExecDestroy(s->exec);
+            (void)hipGraphDestroy(s->graph);
+            s->graph_ready = false;
+        }
+        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int c = enqueue_round(s, st, ttt, true);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (c != DABS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return c;
+        }
+        if (e != hipSuccess) return dabs_fail(DABS_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        HIP_OK(hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0));
+        s->graph = g;
+        s->graph_ready = true;
+        s->ttt = ttt;
+    }
+    for (int r = 0; r < rounds; ++r) HIP_OK(hipGraphLaunch(s->exec, st));
+    return DABS_OK;
+}
+
+extern "C" {
+
+int dabs_batched_create(dabs_problem *const *probs, int32_t nprob, const dabs_ga_params *params,
+                        const int32_t *instances, void *stream, dabs_batched **out) {
+    uint32_t flags = 0;
+    for (int p = 0; params && p < nprob; ++p) flags |= params[p].flags;
+    return batched_create(probs, nprob, params, instances, flags, (hipStream_t)stream, out);
+}
+
+int dabs_batched_destroy(dabs_batched *s) {
+    if (s) batched_free(s);
+    return DABS_OK;
+}
+
+int dabs_batched_run(dabs_batched *s, int32_t rounds, const int64_t *target_e_dev, int32_t use_graph, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
+    return batched_run(s, rounds, target_e_dev, use_graph, (hipStream_t)stream);
+}
+
+int dabs_batched_progress(const dabs_batched *s, int64_t *out_dev, void *stream) {
+    if (!s || !out_dev) return dabs_fail(DABS_E_INVALID, "null argument");
+    hipLaunchKernelGGL(k_progress, dim3((s->nprob + 255) / 256), dim3(256), 0, (hipStream_t)stream, s->d, s->nprob,
+                       out_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+int dabs_batched_pools(const dabs_batched *s, int32_t prob, uint64_t *bits_dev, int64_t *e_dev, int32_t *algo_dev,
+                       int32_t *op_dev, void *stream) {
+    if (!s || prob < 0 || prob >= s->nprob) return dabs_fail(DABS_E_INVALID, "bad batch or problem index");
+    hipStream_t st = (hipStream_t)stream;
+    const ProbDesc &d = s->hdesc[prob];
+    const size_t cells = (size_t)d.g.npools * d.g.capacity;
+    if (bits_dev)
+        HIP_OK(hipMemcpyAsync(bits_dev, s->d.pool_bits + d.pool_word0, cells * d.nw * 8, hipMemcpyDeviceToDevice, st));
+    if (e_dev) HIP_OK(hipMemcpyAsync(e_dev, s->d.pool_e + d.pool_cell0, cells * 8, hipMemcpyDeviceToDevice, st));
+    if (algo_dev)
+        HIP_OK(hipMemcpyAsync(algo_dev, s->d.pool_algo + d.pool_cell0, cells * 4, hipMemcpyDeviceToDevice, st));
+    if (op_dev) HIP_OK(hipMemcpyAsync(op_dev, s->d.pool_op + d.pool_cell0, cells * 4, hipMemcpyDeviceToDevice, st));
+    return DABS_OK;
+}
+
+int dabs_batched_state(const dabs_batched *s, int32_t prob, uint64_t *x_dev, int64_t *e_dev, uint32_t *phase_dev,
+                       void *stream) {
+    if (!s || prob < 0 || prob >= s->nprob) return dabs_fail(DABS_E_INVALID, "bad batch or problem index");
+    hipStream_t st = (hipStream_t)stream;
+    const ProbDesc &d = s->hdesc[prob];
+    const size_t I = d.instances;
+    if (x_dev) HIP_OK(hipMemcpyAsync(x_dev, s->d.x + d.inst_word0, I * d.nw * 8, hipMemcpyDeviceToDevice, st));
+    if (e_dev) HIP_OK(hipMemcpyAsync(e_dev, s->d.e + d.inst0, I * 8, hipMemcpyDeviceToDevice, st));
+    if (phase_dev) HIP_OK(hipMemcpyAsync(phase_dev, s->d.ph + d.inst0, I * 4, hipMemcpyDeviceToDevice, st));
+    return DABS_OK;
+}
+
+int dabs_batched_flips(const dabs_batched *s, int64_t *total_flips_dev, void *stream) {
+    if (!s || !total_flips_dev) return dabs_fail(DABS_E_INVALID, "null argument");
+    HIP_OK(hipMemcpyAsync(total_flips_dev, s->d.ctr, 8, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return DABS_OK;
+}
+
+int dabs_batched_timing(dabs_batched *s, double *out, int32_t reset) {
+    if (!s || !out) return dabs_fail(DABS_E_INVALID, "null argument");
+    if (!s->timed) return dabs_fail(DABS_E_INVALID, "batch created without timing");
+    for (int i = 0; i < s->nev; ++i) {
+        float ms = 0.f;
+        HIP_OK(hipEventSynchronize(s->ev[2 * i + 1]));
+        HIP_OK(hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
+        s->walk_ms += ms;
+        s->walk_launches++;
+    }
+    s->nev = 0;
+    unsigned long long flips = 0;
+    HIP_OK(hipMemcpy(&flips, s->d.ctr, 8, hipMemcpyDeviceToHost));
+    out[0] = s->walk_ms;
+    out[1] = (double)s->walk_launches;
+    out[2] = (double)((long long)flips - s->flips_at_reset);
+    if (reset) {
+        s->walk_ms = 0;
+        s->walk_launches = 0;
+        s->flips_at_reset = (long long)flips;
+    }
+    return DABS_OK;
+}
+
+// ------------------------------------------------- single-problem solver
+struct dabs_solver {
+    dabs_batched *b;
+};
+
+int dabs_solver_create(const dabs_problem *p, const dabs_ga_params *g, int32_t instances, void *stream,
+                       dabs_solver **out) {
+    if (!out) return dabs_fail(DABS_E_INVALID, "null output");
+    dabs_batched *b = nullptr;
+    const int c = check_params(p, g, instances);
+    if (c != DABS_OK) return c;
+    dabs_problem *pp = const_cast<dabs_problem *>(p);
+    const int r = batched_create(&pp, 1, g, &instances, g->flags, (hipStream_t)stream, &b);
+    if (r != DABS_OK) return r;
+    *out = new dabs_solver{b};
+    return DABS_OK;
+}
+
+int dabs_solver_destroy(dabs_solver *s) {
+    if (s) {
+        batched_free(s->b);
+        delete s;
+    }
+    return DABS_OK;
+}
+
+int dabs_solver_run(dabs_solver *s, int32_t rounds, const int64_t *target_e, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return batched_run(s->b, rounds, target_e, 0, (hipStream_t)stream);
+}
+
+int dabs_solver_pools(const dabs_solver *s, uint64_t *bits_dev, int64_t *e_dev, int32_t *algo_dev, int32_t *op_dev,
+                      void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_pools(s->b, 0, bits_dev, e_dev, algo_dev, op_dev, stream);
+}
+
+int dabs_solver_state(const dabs_solver *s, uint64_t *x_dev, int64_t *e_dev, uint32_t *phase_dev,
+                      int64_t *total_flips_dev, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    const int r = dabs_batched_state(s->b, 0, x_dev, e_dev, phase_dev, stream);
+    if (r != DABS_OK || !total_flips_dev) return r;
+    return dabs_batched_flips(s->b, total_flips_dev, stream);
+}
+
+int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_progress(s->b, out_dev, stream);
+}
+
+int dabs_solver_timing(dabs_solver *s, double *out_host, int32_t reset) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_timing(s->b, out_host, reset);
+}
+
+}  // extern "C"

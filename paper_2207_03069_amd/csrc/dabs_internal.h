@@ -46,6 +46,52 @@ struct WalkArgs {
 
 // Launches the walker kernel matching the problem's weight type and size.
 hipError_t launch_walk(const dabs_problem *p, const WalkArgs &a, hipStream_t stream);
+
+// Slot count (power of two) of the walker kernel that serves n bits.
+int walk_slots(int wtype, int n);
+
+// ---------------------------------------------------------------- batches
+// One problem of a batch as the device sees it.  Per-instance arrays of all
+// problems are concatenated: instance i of problem p is global instance
+// inst0 + i; its bit vectors start at word inst_word0 + i * nw.  Pools are
+// concatenated likewise (cells pool_cell0 + q * m + r, words pool_word0 +
+// (q * m + r) * nw).
+struct ProbDesc {
+    const void *W;
+    const int32_t *diag;
+    int64_t ld;
+    int32_t n, nw, wtype, slots;
+    int32_t instances, inst0;
+    int64_t pool_cell0, pool_word0, inst_word0;
+    dabs_ga_params g;
+    int64_t target_e;              // time-to-target energy; INT64_MIN when unset
+    unsigned long long hit;        // ticks of the first E(BEST) <= target_e (atomicMin)
+};
+
+struct BatchDev {
+    ProbDesc *desc;
+    uint64_t *pool_bits;
+    int64_t *pool_e;
+    int32_t *pool_algo, *pool_op;
+    uint64_t *x, *target, *best;   // word arrays
+    int64_t *e, *best_e;
+    uint32_t *ph;
+    int32_t *algo, *op;
+    int32_t *inst_prob;            // global instance -> problem
+    unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round, [3..] work-queue heads
+};
+
+// Batch search of a list of (problem, instance) items by a persistent grid:
+// every wave takes the next item from the queue until the list is exhausted.
+struct ItemsArgs {
+    BatchDev b;
+    const int2 *items;
+    int32_t nitems;
+    unsigned int *queue;
+    int32_t ttt;                   // record time to target
+};
+hipError_t launch_walk_items(int wtype, int slots, const ItemsArgs &a, hipStream_t stream);
+int walk_items_blocks_per_cu(int wtype, int slots);
 // Largest n the walker kernels support for a weight type.
 int max_n(int wtype);
 

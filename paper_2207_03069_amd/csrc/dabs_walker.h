@@ -204,14 +204,24 @@ struct Walker {
     }
 
     // ------------------------------------------------------------- keys
+    // key_j = Delta_j 2^KB + j.  Up to 32 elements per lane the keys are kept
+    // in registers after each flip; above that they are recomputed where used
+    // (one multiply-add), which keeps the walker within the register file.
+    static constexpr bool KEEP = EPL <= 32;
+    __device__ __forceinline__ int K(int j) const {
+        if constexpr (KEEP) return key[j];
+        else return mad24(h[j], s2[j], j);
+    }
     __device__ __forceinline__ void compute_keys() {
+        if constexpr (KEEP) {
 #pragma unroll
-        for (int j = 0; j < EPL; ++j) key[j] = mad24(h[j], s2[j], j);
+            for (int j = 0; j < EPL; ++j) key[j] = mad24(h[j], s2[j], j);
+        }
     }
     __device__ __forceinline__ int lane_min_key() const {
         int m = KEY_BIG;
 #pragma unroll
-        for (int j = 0; j < EPL; j += 2) m = min(m, min(key[j], key[j + 1]));
+        for (int j = 0; j < EPL; j += 2) m = min(m, min(K(j), K(j + 1)));
         return m;
     }
     // least key among elements with ex < thr
@@ -219,8 +229,8 @@ struct Walker {
         int m = KEY_BIG;
 #pragma unroll
         for (int j = 0; j < EPL; j += 2) {
-            const int a = ex[j] < thr ? key[j] : KEY_BIG;
-            const int b = ex[j + 1] < thr ? key[j + 1] : KEY_BIG;
+            const int a = ex[j] < thr ? K(j) : KEY_BIG;
+            const int b = ex[j + 1] < thr ? K(j + 1) : KEY_BIG;
             m = min(m, min(a, b));
         }
         return m;
@@ -323,7 +333,7 @@ struct Walker {
         s.i = i;
         s.L = lidx_to_lane(i);
         s.j = lidx_of(i);
-        s.d = readlane(key[s.j], s.L) >> KB;
+        s.d = readlane(K(s.j), s.L) >> KB;
         return s;
     }
 
@@ -427,8 +437,8 @@ struct Walker {
                     const int j = s * V + e;
                     const uint32_t off = (uint32_t)(gidx(s, e) - lo);
                     const bool in = wrap ? (off >= span) : (off < span);
-                    km = min(km, in && ex[j] < t ? key[j] : KEY_BIG);
-                    kw = min(kw, in ? key[j] : KEY_BIG);
+                    km = min(km, in && ex[j] < t ? K(j) : KEY_BIG);
+                    kw = min(kw, in ? K(j) : KEY_BIG);
                 }
             const int m = wave_min(km >> LOGV);
             const Sel s = empty_dom(m) ? wave_argmin(kw) : argmin_from(km, m);
@@ -453,7 +463,7 @@ struct Walker {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int j = s * V + e;
-                cs[s] += (uint32_t)__builtin_popcountll(ballot(key[j] <= dk && ex[j] < thr));
+                cs[s] += (uint32_t)__builtin_popcountll(ballot(K(j) <= dk && ex[j] < thr));
             }
             c += cs[s];
         }
@@ -479,7 +489,7 @@ struct Walker {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int j = ss * V + e;
-                cm[e] = ballot(key[j] <= dk && ex[j] < thr);
+                cm[e] = ballot(K(j) <= dk && ex[j] < thr);
                 cnt += __builtin_amdgcn_inverse_ballot_w64(cm[e]) ? 1 : 0;
                 excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm[e] >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)cm[e], excl));
@@ -500,7 +510,7 @@ struct Walker {
             out.j = ss * V + e_sel;
             out.i = ss * SPAN + L * V + e_sel;
         });
-        out.d = readlane(key[out.j], out.L) >> KB;
+        out.d = readlane(K(out.j), out.L) >> KB;
         return out;
     }
 
@@ -523,7 +533,7 @@ struct Walker {
             const int mind = mm >> SB;
             int kx = -KEY_BIG;
 #pragma unroll
-            for (int j = 0; j < EPL; ++j) kx = max(kx, ex[j] < thr ? key[j] : -KEY_BIG);
+            for (int j = 0; j < EPL; ++j) kx = max(kx, ex[j] < thr ? K(j) : -KEY_BIG);
             const int maxd = wave_max(kx) >> KB;
             const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
             const uint64_t g = ((uint64_t)(T - t) << 32) / (uint64_t)T;
@@ -545,7 +555,7 @@ struct Walker {
             const int thr = domain(t, km, mm);
             int kp = KEY_BIG;
 #pragma unroll
-            for (int j = 0; j < EPL; ++j) kp = min(kp, (ex[j] < thr && key[j] >= (1 << KB)) ? key[j] : KEY_BIG);
+            for (int j = 0; j < EPL; ++j) kp = min(kp, (ex[j] < thr && K(j) >= (1 << KB)) ? K(j) : KEY_BIG);
             const int pd = wave_min(kp >> LOGV) >> SB;
             const int d = pd >= H_PAD ? H_PAD - 1 : pd;
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
@@ -584,7 +594,7 @@ struct Walker {
                     const int j = s * V + e;
                     const uint32_t word = e < 4 ? wa : wb;
                     const int byte = (int)((word >> (8 * (e & 3))) & 0xFFu);
-                    kr = min(kr, (byte < q && ex[j] < t) ? key[j] : KEY_BIG);
+                    kr = min(kr, (byte < q && ex[j] < t) ? K(j) : KEY_BIG);
                 }
             }
             const int m = wave_min(kr >> LOGV);
@@ -606,38 +616,44 @@ struct Walker {
         return 2 * n - 1;
     }
 
+    // (an if-chain rather than a switch: the switch lets the compiler merge
+    // the tails of the phases, which costs about a hundred VGPRs)
     __device__ __forceinline__ int run_phase(int rule, int T, int tau, uint32_t ph, const uint64_t *target_bits,
                                              int cap) {
         tau = tau < 0 ? 0 : (tau > TAU_MAX ? TAU_MAX : tau);
-        switch (rule) {
-        case GREEDY: return phase_greedy(cap);
-        case STRAIGHT: return phase_straight(target_bits);
-        case MAXMIN: return phase_maxmin(T, tau, ph);
-        case CYCLICMIN: return phase_cyclicmin(T, tau);
-        case RANDOMMIN: return phase_randommin(T, tau, ph);
-        case POSITIVEMIN: return phase_positivemin(T, tau, ph);
-        case TWONEIGHBOR: return phase_twoneighbor();
-        case TABU_GREEDY: return phase_tabu_greedy(T, tau);
-        default: return 0;
-        }
+        int f = 0;
+        if (rule == GREEDY) f = phase_greedy(cap);
+        if (rule == STRAIGHT) f = phase_straight(target_bits);
+        if (rule == MAXMIN) f = phase_maxmin(T, tau, ph);
+        if (rule == CYCLICMIN) f = phase_cyclicmin(T, tau);
+        if (rule == RANDOMMIN) f = phase_randommin(T, tau, ph);
+        if (rule == POSITIVEMIN) f = phase_positivemin(T, tau, ph);
+        if (rule == TWONEIGHBOR) f = phase_twoneighbor();
+        if (rule == TABU_GREEDY) f = phase_tabu_greedy(T, tau);
+        return f;
     }
 
-    // Batch search (Section III-B): Straight -> Greedy -> {main -> Greedy}*.
+    // Batch search (Section III-B): Straight -> Greedy -> {main -> Greedy}*,
+    // written as one loop over phases k = 0, 1, 2, ... (Straight, then Greedy
+    // at odd k and the main algorithm at even k > 0) so that the phases share
+    // one code path and one register allocation.
     __device__ __forceinline__ int batch(const uint64_t *target_bits, int rule, int T, int Bn, int tau, uint32_t &ph,
                                          int cap) {
         bb = xb;
         Eb = E;
         note_best();
         refresh();
-        int f = phase_straight(target_bits);
-        f += phase_greedy(cap);
-        while (f < Bn) {
-            const int fm = run_phase(rule, T, tau, ph, nullptr, cap);
-            if (fm <= 0) break;                       // not a main algorithm: stop
-            f += fm;
-            ph++;
-            f += phase_greedy(cap);
-            if (rule == TWONEIGHBOR) break;
+        const bool main_ok = rule >= MAXMIN && rule <= TWONEIGHBOR;
+        int f = 0;
+        for (int k = 0;; ++k) {
+            const int r = k == 0 ? STRAIGHT : ((k & 1) ? GREEDY : rule);
+            f += run_phase(r, T, tau, ph, target_bits, cap);
+            if (k > 0 && !(k & 1)) ph++;
+            if (k & 1) {
+                // after each Greedy: stop once the batch budget is reached, after
+                // the single TwoNeighbor, or when the rule is not a main algorithm
+                if (f >= Bn || !main_ok || (rule == TWONEIGHBOR && k > 1)) break;
+            }
         }
         return f;
     }
