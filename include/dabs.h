@@ -241,7 +241,7 @@ int dabs_solver_timing(dabs_solver *s, double *out_host, int32_t reset);
 /*
  * Batched solver: many problems of uneven n served by one device loop.  Every
  * round draws the targets of all instances of all problems, runs their batch
- * searches with persistent work-queue kernels (one per weight type and slot
+ * searches (one wavefront per instance, one launch per weight type and slot
  * count, on parallel streams, longest problems first), inserts the packets
  * into each problem's pools and advances the round.  Each problem has its
  * own parameters, pools, instances and generator key (params[p].seed), and

@@ -2,8 +2,8 @@
 // solution pools, for one problem (dabs_solver_*) or many problems of uneven
 // size in one batch (dabs_batched_*).  A round is: target generation for
 // every instance (adaptive operation / algorithm choice, rank selection,
-// genetic operation), one batch search per instance by persistent work-queue
-// kernels (one per slot class, on parallel streams), packet insertion into
+// genetic operation), one batch search per instance (one wavefront each, one
+// launch per slot class, on parallel streams), packet insertion into
 // the pools in instance order, round counter increment.  A batch can capture
 // its round once into a HIP graph and replay it.
 #include <algorithm>
@@ -227,12 +227,6 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     }
 }
 
-// Start of a round: clear the work-queue heads (a kernel, not a memset, so
-// the round can be captured in a graph).
-__global__ void k_round_begin(unsigned long long *ctr, int nq) {
-    if ((int)threadIdx.x < nq) ctr[3 + threadIdx.x] = 0;
-}
-
 __global__ void k_round_end(unsigned long long *ctr) {
     if (threadIdx.x == 0) ctr[2] += 1;
 }
@@ -394,7 +388,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
               hipMalloc(&d.best_e, 8 * (size_t)inst) == hipSuccess && hipMalloc(&d.ph, 4 * (size_t)inst) == hipSuccess &&
               hipMalloc(&d.algo, 4 * (size_t)inst) == hipSuccess && hipMalloc(&d.op, 4 * (size_t)inst) == hipSuccess &&
               hipMalloc(&d.inst_prob, 4 * (size_t)inst) == hipSuccess &&
-              hipMalloc(&d.ctr, 8 * (3 + MAX_CLASSES)) == hipSuccess &&
+              hipMalloc(&d.ctr, 8 * 3) == hipSuccess &&
               hipMalloc(&s->items, sizeof(int2) * items.size()) == hipSuccess &&
               hipMalloc(&s->pool_list, sizeof(int2) * pl.size()) == hipSuccess;
     if (!ok) {
@@ -419,7 +413,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
          hipMemsetAsync(d.x, 0, 8 * (size_t)iwords, st) == hipSuccess &&
          hipMemsetAsync(d.e, 0, 8 * (size_t)inst, st) == hipSuccess &&
          hipMemsetAsync(d.ph, 0, 4 * (size_t)inst, st) == hipSuccess &&
-         hipMemsetAsync(d.ctr, 0, 8 * (3 + MAX_CLASSES), st) == hipSuccess;
+         hipMemsetAsync(d.ctr, 0, 8 * 3, st) == hipSuccess;
     for (int p = 0; p < nprob && ok; ++p) {
         const int64_t total = (int64_t)s->hdesc[p].g.npools * s->hdesc[p].g.capacity * s->hdesc[p].nw;
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
@@ -435,11 +429,9 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
     return DABS_OK;
 }
 
-// One round on stream st: targets, batch searches (one persistent kernel per
-// size class; classes run on parallel streams), packet insertion, round++.
+// One round on stream st: targets, batch searches (one launch per size
+// class; classes run on parallel streams), packet insertion, round++.
 static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturing) {
-    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, st, s->d.ctr, (int)s->classes.size());
-    HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
                        (int)s->total_inst);
     HIP_OK(hipGetLastError());
@@ -459,7 +451,6 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
         a.b = s->d;
         a.items = s->items + s->classes[c].begin;
         a.nitems = s->classes[c].count;
-        a.queue = (unsigned int *)(s->d.ctr + 3 + c);
         a.ttt = ttt;
         HIP_OK(launch_walk_items(s->classes[c].wtype, s->classes[c].slots, a, cs));
         if (nc > 1) HIP_OK(hipEventRecord(s->join[c], cs));

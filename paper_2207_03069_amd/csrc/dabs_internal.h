@@ -78,20 +78,17 @@ struct BatchDev {
     uint32_t *ph;
     int32_t *algo, *op;
     int32_t *inst_prob;            // global instance -> problem
-    unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round, [3..] work-queue heads
+    unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round
 };
 
-// Batch search of a list of (problem, instance) items by a persistent grid:
-// every wave takes the next item from the queue until the list is exhausted.
+// Batch search of a list of (problem, instance) items, one wavefront each.
 struct ItemsArgs {
     BatchDev b;
     const int2 *items;
     int32_t nitems;
-    unsigned int *queue;
     int32_t ttt;                   // record time to target
 };
 hipError_t launch_walk_items(int wtype, int slots, const ItemsArgs &a, hipStream_t stream);
-int walk_items_blocks_per_cu(int wtype, int slots);
 // Largest n the walker kernels support for a weight type.
 int max_n(int wtype);
 

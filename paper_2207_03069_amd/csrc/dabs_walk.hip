@@ -49,63 +49,50 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     }
 }
 
+// One wavefront (one 64-thread workgroup) per (problem, instance) item.  The
+// items of a size class are sorted longest first and the hardware dispatcher
+// hands out workgroups in index order as waves retire, which balances the
+// uneven items without a software queue.  Items are deliberately not popped
+// from an atomic counter inside a loop: with a lane-0 epilogue in the same
+// loop, the compiler may split it into nested loops so that lanes 1..63
+// re-enter the pop without lane 0 (and read item 0 again, forever).
 template <typename WT, int SLOTS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_items(ItemsArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_items(ItemsArgs a) {
     typedef typename Walker<WT, SLOTS>::vecE vecE;
     vecE h, s2, ex, key;
     const int lane = lane_id();
     const BatchDev &b = a.b;
-    for (;;) {
-        unsigned int it = 0;
-        if (lane == 0) it = atomicAdd(a.queue, 1u);
-        it = (unsigned int)__builtin_amdgcn_readfirstlane((int)it);
-        if (it >= (unsigned int)a.nitems) break;            // every wave leaves once the list is done
-        const int2 item = a.items[it];
-        const int p = __builtin_amdgcn_readfirstlane(item.x), i = __builtin_amdgcn_readfirstlane(item.y);
-        ProbDesc *d = b.desc + p;
-        Walker<WT, SLOTS> w(h, s2, ex, key);
-        w.setup((const WT *)d->W, d->diag, d->ld, d->n, d->g.seed, (uint32_t)i);
-        const int64_t gi = d->inst0 + i;
-        const int64_t wo = d->inst_word0 + (int64_t)i * d->nw;
-        w.load_x(b.x + wo);
-        if (a.ttt && d->target_e != INT64_MIN) {
-            w.hit = &d->hit;
-            w.target = d->target_e;
-            w.t0 = b.ctr[1];
-            w.hit_done = false;
-        }
-        uint32_t ph = b.ph[gi];
-        const int f = w.batch(b.target + wo, b.algo[gi], d->g.T, d->g.Bn, d->g.tau, ph, d->g.greedy_cap);
-        w.store_bits(w.xb, b.x + wo);
-        w.store_bits(w.bb, b.best + wo);
-        if (lane == 0) {
-            b.ph[gi] = ph;
-            b.e[gi] = w.E;
-            b.best_e[gi] = w.Eb;
-            atomicAdd(&b.ctr[0], (unsigned long long)f);
-        }
+    const int2 item = a.items[blockIdx.x];
+    const int p = __builtin_amdgcn_readfirstlane(item.x), i = __builtin_amdgcn_readfirstlane(item.y);
+    ProbDesc *d = b.desc + p;
+    Walker<WT, SLOTS> w(h, s2, ex, key);
+    w.setup((const WT *)d->W, d->diag, d->ld, d->n, d->g.seed, (uint32_t)i);
+    const int64_t gi = d->inst0 + i;
+    const int64_t wo = d->inst_word0 + (int64_t)i * d->nw;
+    w.load_x(b.x + wo);
+    if (a.ttt && d->target_e != INT64_MIN) {
+        w.hit = &d->hit;
+        w.target = d->target_e;
+        w.t0 = b.ctr[1];
+        w.hit_done = false;
+    }
+    uint32_t ph = b.ph[gi];
+    const int f = w.batch(b.target + wo, b.algo[gi], d->g.T, d->g.Bn, d->g.tau, ph, d->g.greedy_cap);
+    w.store_bits(w.xb, b.x + wo);
+    w.store_bits(w.bb, b.best + wo);
+    if (lane == 0) {
+        b.ph[gi] = ph;
+        b.e[gi] = w.E;
+        b.best_e[gi] = w.Eb;
+        atomicAdd(&b.ctr[0], (unsigned long long)f);
     }
 }
 
 template <typename WT, int SLOTS>
 static hipError_t go_items(const ItemsArgs &a, hipStream_t st) {
-    int dev = 0, cus = 0, per = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_walk_items<WT, SLOTS>, 256, 0);
-    int blocks = cus * (per > 0 ? per : 1);
-    const int need = (a.nitems + 3) / 4;
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_walk_items<WT, SLOTS>), dim3(blocks), dim3(256), 0, st, a);
+    if (a.nitems < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_walk_items<WT, SLOTS>), dim3(a.nitems), dim3(WAVE), 0, st, a);
     return hipGetLastError();
-}
-
-template <typename WT, int SLOTS>
-static int per_cu() {
-    int per = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_walk_items<WT, SLOTS>, 256, 0);
-    return per;
 }
 
 int walk_slots(int wtype, int n) {
@@ -132,25 +119,6 @@ hipError_t launch_walk_items(int wtype, int slots, const ItemsArgs &a, hipStream
     case 4: return go_items<int32_t, 4>(a, st);
     case 8: return go_items<int32_t, 8>(a, st);
     default: return hipErrorInvalidValue;
-    }
-}
-
-int walk_items_blocks_per_cu(int wtype, int slots) {
-    if (wtype == DABS_W_I16) {
-        switch (slots) {
-        case 1: return per_cu<int16_t, 1>();
-        case 2: return per_cu<int16_t, 2>();
-        case 4: return per_cu<int16_t, 4>();
-        case 8: return per_cu<int16_t, 8>();
-        default: return 0;
-        }
-    }
-    switch (slots) {
-    case 1: return per_cu<int32_t, 1>();
-    case 2: return per_cu<int32_t, 2>();
-    case 4: return per_cu<int32_t, 4>();
-    case 8: return per_cu<int32_t, 8>();
-    default: return 0;
     }
 }
 
