@@ -124,7 +124,7 @@ def main():
     achieved_ops = walk_flips * ops_per_flip / walk_s
     roofline = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "Tops/s (int32 lane-ops)", "frac": achieved_ops / VALU_PEAK_OPS, "traffic": None,
-                "kernel": "k_walk (batch search)", "launches": launches,
+                "kernel": "k_walk_items (batch search, one wavefront per instance)", "launches": launches,
                 "avg_launch_ms": walk_ms / max(launches, 1),
                 "w_row_bytes_per_s": walk_flips * bytes_per_flip / walk_s / 1e9,
                 "w_row_unit": "GB/s of W rows (L2-resident, 1.28 MB)"}

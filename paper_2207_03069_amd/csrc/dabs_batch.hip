@@ -272,6 +272,7 @@ struct dabs_batched {
     std::vector<Cls> classes;
     hipStream_t side[MAX_CLASSES];
     hipEvent_t fork, join[MAX_CLASSES];
+    hipStream_t cap;                   // capture stream (the caller's may be the null stream)
     hipGraph_t graph;
     hipGraphExec_t exec;
     bool graph_ready;
@@ -295,6 +296,7 @@ static void batched_free(dabs_batched *s) {
         if (s->join[i]) (void)hipEventDestroy(s->join[i]);
     }
     if (s->fork) (void)hipEventDestroy(s->fork);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
     for (int i = 0; i < 2 * dabs_batched::NEV; ++i)
         if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
     void *ptrs[] = {s->d.desc, s->d.pool_bits, s->d.pool_e, s->d.pool_algo, s->d.pool_op, s->d.x, s->d.target,
@@ -396,7 +398,8 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         return dabs_fail(DABS_E_NOMEM, "batch allocation failed");
     }
     s->timed = (flags & DABS_SOLVER_TIME_WALK) != 0;
-    ok = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming) == hipSuccess;
+    ok = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming) == hipSuccess &&
+         hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) == hipSuccess;
     for (size_t c = 0; c < s->classes.size() && ok; ++c)
         ok = hipStreamCreateWithFlags(&s->side[c], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&s->join[c], hipEventDisableTiming) == hipSuccess;
@@ -485,10 +488,12 @@ static int batched_run(dabs_batched *s, int rounds, const int64_t *target_e, int
             (void)hipGraphDestroy(s->graph);
             s->graph_ready = false;
         }
-        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const int c = enqueue_round(s, st, ttt, true);
+        // captured on the batch's own stream (the legacy null stream cannot
+        // capture); nothing runs during capture, the replays go to st
+        HIP_OK(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+        const int c = enqueue_round(s, s->cap, ttt, true);
         hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(st, &g);
+        const hipError_t e = hipStreamEndCapture(s->cap, &g);
         if (c != DABS_OK) {
             if (g) (void)hipGraphDestroy(g);
             return c;
