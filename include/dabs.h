@@ -56,10 +56,13 @@ typedef enum {
 } dabs_rule;
 
 /* Genetic operations: Section IV-A (Random, Best, Mutation, Crossover, Zero,
- * One, IntervalZero) and IV-B (Xrossover). */
+ * One, IntervalZero) and IV-B (Xrossover); MLP-seed and MLP-mutate are the
+ * learned proposal's operations (they need an MLP attached to the solver, see
+ * dabs_mlp_*), added to the adaptive choice of Section IV-A like any other. */
 typedef enum {
     DABS_OP_RANDOM = 0, DABS_OP_BEST = 1, DABS_OP_MUTATION = 2, DABS_OP_CROSSOVER = 3,
-    DABS_OP_XROSSOVER = 4, DABS_OP_ZERO = 5, DABS_OP_ONE = 6, DABS_OP_INTERVALZERO = 7
+    DABS_OP_XROSSOVER = 4, DABS_OP_ZERO = 5, DABS_OP_ONE = 6, DABS_OP_INTERVALZERO = 7,
+    DABS_OP_MLP_SEED = 8, DABS_OP_MLP_MUTATE = 9
 } dabs_op;
 
 typedef struct dabs_problem dabs_problem;
@@ -273,6 +276,70 @@ int dabs_batched_state(const dabs_batched *b, int32_t prob, uint64_t *x_dev, int
 int dabs_batched_flips(const dabs_batched *b, int64_t *total_flips_dev, void *stream);
 /* As dabs_solver_timing (DABS_SOLVER_TIME_WALK in any problem's flags). */
 int dabs_batched_timing(dabs_batched *b, double *out_host, int32_t reset);
+
+/*
+ * Learned proposal.  Not in the paper: a small network that scores every bit
+ * of a pooled vector and two genetic operations that use the scores; the
+ * exact search of Section III stays the judge (energies are never
+ * approximated) and the adaptive operation choice of Section IV-A decides how
+ * often the learned operations are used.
+ *
+ * Features of bit k of pooled vector X (pool q, rank r, capacity m), float32
+ * expressions rounded to bfloat16 (round to nearest even):
+ *   f0 = Delta_k(X)/B (Eq. (3), B the problem's Delta bound), f1 = 2x_k - 1,
+ *   f2 = W_kk/B, f3 = R_k/B with R_k = |W_kk| + 2 sum_{j != k} |W_kj|,
+ *   f4 = 2 c_k/m - 1 (c_k entries of pool q with bit k set), f5 = f1 f4,
+ *   f6 = 2 b_k - 1 (b the pool's rank-0 entry), f7 = r/m.
+ * Network: z = W3 relu(W2 relu(W1 f + b1) + b2) + b3, 8 -> 64 -> 64 -> 1.
+ * Weights and activations are bfloat16 on the matrix cores, accumulation and
+ * biases float32; the float32 master parameters (4801) are laid out
+ * W1[64][8] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3.
+ * Training minimises the mean binary cross-entropy with logits (label 1 = the
+ * bit differs from a reference vector, e.g. the best vector a plain search
+ * found later) with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ *   MLP-seed:   target = parent with every bit of positive logit flipped.
+ *   MLP-mutate: flip bit k when its per-bit u32 draw (the genetic operations'
+ *               stream: Philox counter (round, instance, k/4, 4<<24 | 2),
+ *               word k mod 4) is below 2^29 + q_k 2^22,
+ *               q_k = clamp(round-half-even(16 z_k), -128, 127).
+ */
+typedef struct dabs_mlp dabs_mlp;
+#define DABS_MLP_PARAMS 4801
+/* params_host: nullable float32[4801] initial parameters (zeros if NULL). */
+int dabs_mlp_create(const float *params_host, dabs_mlp **out);
+int dabs_mlp_destroy(dabs_mlp *m);
+/* Copies the float32 master parameters to params_dev[4801]. */
+int dabs_mlp_params(const dabs_mlp *m, float *params_dev, void *stream);
+/* Features of every entry of npools pools of `capacity` entries:
+ * pool_bits_dev [npools][capacity][ceil(n/64)] u64, feat_dev
+ * [npools][capacity][n][8] bfloat16 bit patterns.  n <= 4096.  Synchronises
+ * the stream. */
+int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev, int32_t npools, int32_t capacity,
+                           uint16_t *feat_dev, void *stream);
+/* labels_dev[e][k] = bit k of bits_dev[e] != bit k of ref_dev (u8, count x n). */
+int dabs_mlp_labels(const dabs_problem *p, const uint64_t *bits_dev, int64_t count, const uint64_t *ref_dev,
+                    uint8_t *labels_dev, void *stream);
+/* logits_dev[count] float32 of the samples feat_dev[count][8]. */
+int dabs_mlp_forward(const dabs_mlp *m, int64_t count, const uint16_t *feat_dev, float *logits_dev, void *stream);
+/* Gradient of the mean loss over `count` samples into the network's gradient
+ * buffer; optional copies to grad_dev[4801] and loss_dev[1] (float32). */
+int dabs_mlp_grad(dabs_mlp *m, int64_t count, const uint16_t *feat_dev, const uint8_t *labels_dev, float *grad_dev,
+                  float *loss_dev, void *stream);
+/* One Adam step with the gradient buffer (step count kept by the network). */
+int dabs_mlp_adam(dabs_mlp *m, float lr, void *stream);
+/* dabs_mlp_grad then dabs_mlp_adam. */
+int dabs_mlp_train_step(dabs_mlp *m, int64_t count, const uint16_t *feat_dev, const uint8_t *labels_dev, float lr,
+                        float *loss_dev, void *stream);
+/* One MLP operation (DABS_OP_MLP_SEED / _MUTATE) on `count` parents
+ * [count][ceil(n/64)] with their logits [count][n]; parent i uses instance
+ * number inst0 + i and the given round in the draw counters. */
+int dabs_mlp_apply_op(int32_t op, int32_t n, int32_t count, const uint64_t *parent_dev, const float *logits_dev,
+                      uint64_t seed, uint32_t round, uint32_t inst0, uint64_t *out_dev, void *stream);
+/* Attach (or detach with NULL) the network whose logits the MLP operations
+ * use: every round then scores all pooled vectors before target generation.
+ * The network must outlive the solver / batch or be detached first. */
+int dabs_solver_set_mlp(dabs_solver *s, const dabs_mlp *m);
+int dabs_batched_set_mlp(dabs_batched *b, const dabs_mlp *m);
 
 #ifdef __cplusplus
 }

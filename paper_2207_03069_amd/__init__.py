@@ -20,7 +20,8 @@ DABS_W_I16, DABS_W_I32 = 0, 1
 (DABS_GREEDY, DABS_STRAIGHT, DABS_MAXMIN, DABS_CYCLICMIN, DABS_RANDOMMIN, DABS_POSITIVEMIN,
  DABS_TWONEIGHBOR, DABS_TABU_GREEDY) = range(8)
 (DABS_OP_RANDOM, DABS_OP_BEST, DABS_OP_MUTATION, DABS_OP_CROSSOVER, DABS_OP_XROSSOVER, DABS_OP_ZERO,
- DABS_OP_ONE, DABS_OP_INTERVALZERO) = range(8)
+ DABS_OP_ONE, DABS_OP_INTERVALZERO, DABS_OP_MLP_SEED, DABS_OP_MLP_MUTATE) = range(10)
+DABS_MLP_PARAMS = 4801
 MAIN_ALGOS = (DABS_MAXMIN, DABS_CYCLICMIN, DABS_RANDOMMIN, DABS_POSITIVEMIN, DABS_TWONEIGHBOR)
 
 
@@ -80,6 +81,19 @@ _SIGS = {
     "dabs_batched_state": ([_P, C.c_int32, _P, _P, _P, _P], C.c_int),
     "dabs_batched_flips": ([_P, _P, _P], C.c_int),
     "dabs_batched_timing": ([_P, C.POINTER(C.c_double), C.c_int32], C.c_int),
+    "dabs_mlp_create": ([_P, C.POINTER(_P)], C.c_int),
+    "dabs_mlp_destroy": ([_P], C.c_int),
+    "dabs_mlp_params": ([_P, _P, _P], C.c_int),
+    "dabs_mlp_pool_features": ([_P, _P, C.c_int32, C.c_int32, _P, _P], C.c_int),
+    "dabs_mlp_labels": ([_P, _P, C.c_int64, _P, _P, _P], C.c_int),
+    "dabs_mlp_forward": ([_P, C.c_int64, _P, _P, _P], C.c_int),
+    "dabs_mlp_grad": ([_P, C.c_int64, _P, _P, _P, _P, _P], C.c_int),
+    "dabs_mlp_adam": ([_P, C.c_float, _P], C.c_int),
+    "dabs_mlp_train_step": ([_P, C.c_int64, _P, _P, C.c_float, _P, _P], C.c_int),
+    "dabs_mlp_apply_op": ([C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_uint64, C.c_uint32, C.c_uint32, _P, _P],
+                          C.c_int),
+    "dabs_solver_set_mlp": ([_P, _P], C.c_int),
+    "dabs_batched_set_mlp": ([_P, _P], C.c_int),
 }
 
 _lib = None
@@ -305,3 +319,77 @@ def dabs_batched_timing(b: Batched, reset: bool = False):
     out = (C.c_double * 3)()
     _check(lib().dabs_batched_timing(b.handle, out, int(reset)))
     return out[0], int(out[1]), int(out[2])
+
+
+# ------------------------------------------------------------------ learned proposal
+class Mlp:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.dabs_mlp_destroy(h)
+
+
+def dabs_mlp_create(params=None) -> Mlp:
+    """params: optional float32 array of DABS_MLP_PARAMS initial values (host)."""
+    import numpy as np
+    h = C.c_void_p()
+    buf = None
+    if params is not None:
+        buf = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if buf.shape != (DABS_MLP_PARAMS,):
+            raise ValueError("need %d parameters" % DABS_MLP_PARAMS)
+    _check(lib().dabs_mlp_create(None if buf is None else buf.ctypes.data_as(C.c_void_p), C.byref(h)))
+    return Mlp(h)
+
+
+def dabs_mlp_destroy(m: Mlp):
+    h, m.handle = m.handle, None
+    if h:
+        _check(lib().dabs_mlp_destroy(h))
+
+
+def dabs_mlp_params(m: Mlp, out, stream=None):
+    _check(lib().dabs_mlp_params(m.handle, _ptr(out), _stream(stream)))
+
+
+def dabs_mlp_pool_features(p: Problem, pool_bits, npools: int, capacity: int, feat, stream=None):
+    _check(lib().dabs_mlp_pool_features(p.handle, _ptr(pool_bits), npools, capacity, _ptr(feat), _stream(stream)))
+
+
+def dabs_mlp_labels(p: Problem, bits, count: int, ref, labels, stream=None):
+    _check(lib().dabs_mlp_labels(p.handle, _ptr(bits), count, _ptr(ref), _ptr(labels), _stream(stream)))
+
+
+def dabs_mlp_forward(m: Mlp, count: int, feat, logits, stream=None):
+    _check(lib().dabs_mlp_forward(m.handle, count, _ptr(feat), _ptr(logits), _stream(stream)))
+
+
+def dabs_mlp_grad(m: Mlp, count: int, feat, labels, grad=None, loss=None, stream=None):
+    _check(lib().dabs_mlp_grad(m.handle, count, _ptr(feat), _ptr(labels), _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def dabs_mlp_adam(m: Mlp, lr: float, stream=None):
+    _check(lib().dabs_mlp_adam(m.handle, lr, _stream(stream)))
+
+
+def dabs_mlp_train_step(m: Mlp, count: int, feat, labels, lr: float, loss=None, stream=None):
+    _check(lib().dabs_mlp_train_step(m.handle, count, _ptr(feat), _ptr(labels), lr, _ptr(loss), _stream(stream)))
+
+
+def dabs_mlp_apply_op(op: int, n: int, count: int, parents, logits, seed: int, round: int, inst0: int, out,
+                      stream=None):
+    _check(lib().dabs_mlp_apply_op(op, n, count, _ptr(parents), _ptr(logits), seed, round, inst0, _ptr(out),
+                                   _stream(stream)))
+
+
+def dabs_solver_set_mlp(s: Solver, m):
+    _check(lib().dabs_solver_set_mlp(s.handle, None if m is None else m.handle))
+    s.mlp = m                                   # keep the network alive while attached
+
+
+def dabs_batched_set_mlp(b: Batched, m):
+    _check(lib().dabs_batched_set_mlp(b.handle, None if m is None else m.handle))
+    b.mlp = m

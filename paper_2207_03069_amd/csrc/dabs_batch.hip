@@ -146,6 +146,14 @@ __global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
         case DABS_OP_ONE:
             t = A | thresh_word(g.seed, rd, (uint32_t)inst, w, g.p_one);
             break;
+        case DABS_OP_MLP_SEED:
+        case DABS_OP_MLP_MUTATE:
+            // learned operations on parent A, scored by A's logits
+            t = b.pool_logits ? mlp_op_word(op, A, b.pool_logits + d.pool_bit0 +
+                                                       ((int64_t)q * m + rank_index(v.w[0], (uint32_t)m)) * n,
+                                            n, w, g.seed, rd, (uint32_t)inst)
+                              : A;
+            break;
         case DABS_OP_INTERVALZERO: {
             // zero positions st .. st+len-1 (mod n)
             const uint32_t len = lo32 + scale32(v.w[2], hi32 - lo32 + 1);
@@ -263,6 +271,13 @@ __global__ void k_progress(BatchDev b, int nprob, int64_t *out) {
 struct dabs_batched {
     int nprob;
     std::vector<ProbDesc> hdesc;
+    std::vector<const dabs_problem *> probs;
+    // learned proposal: the network and its per-round scratch
+    const dabs_mlp *mlp;
+    bool mlp_ops;                      // some problem enables an MLP operation
+    int *mlp_cnt;
+    short *mlp_feat;
+    float *mlp_logits;
     int64_t total_inst, pool_cells, pool_words, inst_words;
     BatchDev d;
     int2 *items;                       // device, grouped by class
@@ -303,6 +318,9 @@ static void batched_free(dabs_batched *s) {
                     s->d.best, s->d.e, s->d.best_e, s->d.ph, s->d.algo, s->d.op, s->d.inst_prob, s->d.ctr,
                     s->items, s->pool_list};
     for (void *q : ptrs) (void)hipFree(q);
+    (void)hipFree(s->mlp_cnt);
+    (void)hipFree(s->mlp_feat);
+    (void)hipFree(s->mlp_logits);
     delete s;
 }
 
@@ -316,7 +334,7 @@ static int check_params(const dabs_problem *p, const dabs_ga_params *g, int inst
         if (g->algos[i] < DABS_MAXMIN || g->algos[i] > DABS_TWONEIGHBOR)
             return dabs_fail(DABS_E_INVALID, "algorithm %d is not a main search algorithm", g->algos[i]);
     for (int i = 0; i < g->n_ops; ++i)
-        if (g->ops[i] < DABS_OP_RANDOM || g->ops[i] > DABS_OP_INTERVALZERO)
+        if (g->ops[i] < DABS_OP_RANDOM || g->ops[i] > DABS_OP_MLP_MUTATE)
             return dabs_fail(DABS_E_INVALID, "bad genetic operation %d", g->ops[i]);
     if (g->T < 1 || g->Bn < 0 || g->tau < 0 || g->tau > TAU_MAX) return dabs_fail(DABS_E_INVALID, "bad T / Bn / tau");
     if (g->crossover_kind != 0 && g->crossover_kind != 1) return dabs_fail(DABS_E_INVALID, "bad crossover kind");
@@ -333,11 +351,15 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
     dabs_batched *s = new dabs_batched();
     s->nprob = nprob;
     s->hdesc.resize(nprob);
-    int64_t inst = 0, cells = 0, pwords = 0, iwords = 0;
+    int64_t inst = 0, cells = 0, pwords = 0, iwords = 0, pbits = 0;
     for (int p = 0; p < nprob; ++p) {
         ProbDesc &d = s->hdesc[p];
         memset(&d, 0, sizeof(d));
         const dabs_problem *pr = probs[p];
+        s->probs.push_back(pr);
+        for (int i = 0; i < params[p].n_ops; ++i)
+            if (params[p].ops[i] == DABS_OP_MLP_SEED || params[p].ops[i] == DABS_OP_MLP_MUTATE) s->mlp_ops = true;
+        d.pool_bit0 = pbits;
         d.W = pr->W; d.diag = pr->diag; d.ld = pr->ld; d.n = pr->n; d.nw = (pr->n + 63) / 64;
         d.wtype = pr->wtype; d.slots = walk_slots(pr->wtype, pr->n);
         d.instances = instances[p]; d.inst0 = (int32_t)inst;
@@ -346,6 +368,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         d.target_e = INT64_MIN; d.hit = ~0ull;
         const int64_t pc = (int64_t)d.g.npools * d.g.capacity;
         inst += d.instances; cells += pc; pwords += pc * d.nw; iwords += (int64_t)d.instances * d.nw;
+        pbits += pc * d.n;
     }
     s->total_inst = inst; s->pool_cells = cells; s->pool_words = pwords; s->inst_words = iwords;
     // items grouped by (wtype, slots), longest first inside a class
@@ -435,6 +458,13 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
 // One round on stream st: targets, batch searches (one launch per size
 // class; classes run on parallel streams), packet insertion, round++.
 static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturing) {
+    if (s->mlp)
+        for (int p = 0; p < s->nprob; ++p) {
+            const ProbDesc &d = s->hdesc[p];
+            const int r = mlp_pool_logits(s->probs[p], s->mlp, s->d.pool_bits + d.pool_word0, d.g.npools,
+                                          d.g.capacity, s->mlp_cnt, s->mlp_feat, s->mlp_logits + d.pool_bit0, st);
+            if (r != DABS_OK) return r;
+        }
     hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
                        (int)s->total_inst);
     HIP_OK(hipGetLastError());
@@ -472,6 +502,7 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
 
 static int batched_run(dabs_batched *s, int rounds, const int64_t *target_e, int use_graph, hipStream_t st) {
     if (rounds < 0) return dabs_fail(DABS_E_INVALID, "rounds < 0");
+    if (s->mlp_ops && !s->mlp) return dabs_fail(DABS_E_INVALID, "MLP operations enabled but no network attached");
     const int ttt = target_e ? 1 : 0;
     hipLaunchKernelGGL(k_run_begin, dim3((s->nprob + 255) / 256), dim3(256), 0, st, s->d, s->nprob, target_e);
     HIP_OK(hipGetLastError());
@@ -592,6 +623,33 @@ int dabs_batched_timing(dabs_batched *s, double *out, int32_t reset) {
     return DABS_OK;
 }
 
+int dabs_batched_set_mlp(dabs_batched *s, const dabs_mlp *m) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
+    if (m && !s->mlp_logits) {
+        int64_t cnt = 0, feat = 0, bits = 0;
+        for (int p = 0; p < s->nprob; ++p) {
+            const ProbDesc &d = s->hdesc[p];
+            if (d.n > 4096) return dabs_fail(DABS_E_UNSUPPORTED, "the learned proposal needs n <= 4096");
+            const int64_t pc = (int64_t)d.g.npools * d.g.capacity;
+            cnt = std::max<int64_t>(cnt, (int64_t)d.g.npools * d.n);
+            feat = std::max<int64_t>(feat, pc * d.n * 8);
+            bits += pc * d.n;
+        }
+        if (hipMalloc(&s->mlp_cnt, sizeof(int) * cnt) != hipSuccess ||
+            hipMalloc(&s->mlp_feat, sizeof(short) * feat) != hipSuccess ||
+            hipMalloc(&s->mlp_logits, sizeof(float) * bits) != hipSuccess)
+            return dabs_fail(DABS_E_NOMEM, "learned-proposal scratch allocation failed");
+    }
+    s->mlp = m;
+    s->d.pool_logits = m ? s->mlp_logits : nullptr;
+    if (s->graph_ready) {            // the captured round has the old kernel arguments
+        (void)hipGraphExecDestroy(s->exec);
+        (void)hipGraphDestroy(s->graph);
+        s->graph_ready = false;
+    }
+    return DABS_OK;
+}
+
 // ------------------------------------------------- single-problem solver
 struct dabs_solver {
     dabs_batched *b;
@@ -608,6 +666,11 @@ int dabs_solver_create(const dabs_problem *p, const dabs_ga_params *g, int32_t i
     if (r != DABS_OK) return r;
     *out = new dabs_solver{b};
     return DABS_OK;
+}
+
+int dabs_solver_set_mlp(dabs_solver *s, const dabs_mlp *m) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_set_mlp(s->b, m);
 }
 
 int dabs_solver_destroy(dabs_solver *s) {

@@ -181,8 +181,8 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
         dabs_fail(DABS_E_HIP, "validating W failed");
     }
     hipFree(bad);
-    hipFree(rowb);
     if (status != DABS_OK) {
+        hipFree(rowb);
         hipFree(Wp);
         hipFree(diag);
         return status;
@@ -194,6 +194,7 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     p->bound = bound;
     p->W = Wp;
     p->diag = diag;
+    p->rowabs = (int64_t *)rowb;
     p->device = dev;
     *out = p;
     return DABS_OK;
@@ -201,8 +202,9 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
 
 int dabs_problem_destroy(dabs_problem *p) {
     if (!p) return DABS_OK;
-    hipFree(p->W);
-    hipFree(p->diag);
+    (void)hipFree(p->W);
+    (void)hipFree(p->diag);
+    (void)hipFree(p->rowabs);
     delete p;
     return DABS_OK;
 }

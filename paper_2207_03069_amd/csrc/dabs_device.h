@@ -126,4 +126,42 @@ __device__ __forceinline__ int mad24(int a, int b, int c) {
 
 typedef short short2v __attribute__((ext_vector_type(2)));
 
+// ---------------------------------------------------------------------------
+// Genetic operations driven by the learned logits of the parent's bits
+// (word w of the target):
+//   MLP-seed   flips bit k when z_k > 0;
+//   MLP-mutate flips bit k when its u32 draw is below 2^29 + q_k 2^22 with
+//              q_k = clamp(round-half-even(16 z_k), -128, 127), i.e. with
+//              probability (1 + q_k/128)/8 around the Mutation rate 1/8.
+// The draws are the genetic operations' per-bit stream: Philox counter
+// (round, instance, k/4, TAG_GA<<24 | 2), word k mod 4.
+// ---------------------------------------------------------------------------
+enum { OP_MLP_SEED = 8, OP_MLP_MUTATE = 9 };
+
+__device__ __forceinline__ uint64_t mlp_op_word(int op, uint64_t parent, const float *logits, int n, int w,
+                                                uint64_t seed, uint32_t rd, uint32_t inst) {
+    uint64_t flip = 0;
+    const int k0 = 64 * w;
+    for (int c = 0; c < 16; ++c) {
+        if (k0 + 4 * c >= n) break;
+        R4 r = {{0u, 0u, 0u, 0u}};
+        if (op == OP_MLP_MUTATE) r = philox(rd, inst, (uint32_t)(16 * w + c), ((uint32_t)TAG_GA << 24) | 2u, seed);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + 4 * c + q;
+            if (k >= n) break;
+            const float z = logits[k];
+            bool f;
+            if (op == OP_MLP_SEED) {
+                f = z > 0.0f;
+            } else {
+                const float lv = fminf(fmaxf(rintf(z * 16.0f), -128.0f), 127.0f);
+                f = (long long)r.w[q] < (1ll << 29) + (long long)lv * (1ll << 22);
+            }
+            if (f) flip |= 1ull << (4 * c + q);
+        }
+    }
+    return parent ^ flip;
+}
+
 }  // namespace dabs

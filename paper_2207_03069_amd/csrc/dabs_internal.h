@@ -13,6 +13,7 @@ struct dabs_problem {
     int64_t bound;       // max_k |W_kk| + 2 sum_{j!=k} |W_kj|
     void *W;             // device, n rows x ld, zero diagonal, zero padding
     int32_t *diag;       // device, n
+    int64_t *rowabs;     // device, n: R_k = |W_kk| + 2 sum_{j != k} |W_kj|
     int device;
 };
 
@@ -63,6 +64,7 @@ struct ProbDesc {
     int32_t n, nw, wtype, slots;
     int32_t instances, inst0;
     int64_t pool_cell0, pool_word0, inst_word0;
+    int64_t pool_bit0;             // first logit of the problem's pooled bits (cells x n)
     dabs_ga_params g;
     int64_t target_e;              // time-to-target energy; INT64_MIN when unset
     unsigned long long hit;        // ticks of the first E(BEST) <= target_e (atomicMin)
@@ -78,6 +80,7 @@ struct BatchDev {
     uint32_t *ph;
     int32_t *algo, *op;
     int32_t *inst_prob;            // global instance -> problem
+    const float *pool_logits;      // nullable: learned logits of every pooled bit
     unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round
 };
 
@@ -92,6 +95,13 @@ hipError_t launch_walk_items(int wtype, int slots, const ItemsArgs &a, hipStream
 // Largest n the walker kernels support for a weight type.
 int max_n(int wtype);
 
+}  // namespace dabs
+
+namespace dabs {
+// Features and (with a network) logits of every entry of P pools of capacity
+// m (dabs_mlp.hip); cnt [P][n] int and feat [P m n][8] bfloat16 are scratch.
+int mlp_pool_logits(const dabs_problem *p, const dabs_mlp *net, const uint64_t *pool_bits, int P, int m, int *cnt,
+                    short *feat, float *logits, hipStream_t st);
 }  // namespace dabs
 
 // Thread-local error text (dabs_capi.hip).

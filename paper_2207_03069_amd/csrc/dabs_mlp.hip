@@ -1,0 +1,560 @@
+// dabs_mlp.hip -- the learned proposal: per-bit features of pooled vectors,
+// a 3-layer MLP (8 -> 64 -> 64 -> 1, ReLU) giving flip-priority logits, its
+// training (binary cross-entropy, Adam) and the two genetic operations that
+// consume the logits (MLP-seed, MLP-mutate).
+//
+// Matrix products run on the matrix cores: v_mfma_f32_16x16x16_bf16 with
+// bfloat16 operands (round to nearest even) and float32 accumulation.
+// Operand layouts of that instruction, lane l = 0..63, g = l / 16, c = l % 16:
+//   A[i][k] (16 x 16): lane i + 16 floor(k/4), element k mod 4
+//   B[k][j] (16 x 16): lane j + 16 floor(k/4), element k mod 4
+//   D[i][j] (16 x 16): lane j + 16 floor(i/4), element i mod 4
+// Activations are kept transposed (hidden unit x sample): a layer's output
+// tile D (16 units x 16 samples) is then, element for element, the B operand
+// of the next layer's 16-unit slice of its reduction, so the forward pass
+// needs no data movement between layers.  The weight gradients reduce over
+// samples and need the transposed tiles; each wavefront stages them through
+// its own 6.3 KB of LDS.
+#include <math.h>
+#include <string.h>
+
+#include "dabs_device.h"
+#include "dabs_internal.h"
+
+#define HIP_OK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return dabs_fail(DABS_E_HIP, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+namespace dabs {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NF = 8, HID = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 4736, OFF_B3 = 4800;
+constexpr int NPAR = 4801;
+constexpr int GRAD_BLOCKS_MAX = 1024;
+constexpr float ADAM_B1 = 0.9f, ADAM_B2 = 0.999f, ADAM_EPS = 1e-8f;
+
+// float32 -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ short to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(short b) { return __uint_as_float((uint32_t)(uint16_t)b << 16); }
+
+__device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// four consecutive bfloat16 values (8-byte aligned)
+__device__ __forceinline__ bf16x4 ld4(const short *p) {
+    const uint2 u = *(const uint2 *)p;
+    bf16x4 v;
+    v.x = (short)(u.x & 0xFFFF); v.y = (short)(u.x >> 16);
+    v.z = (short)(u.y & 0xFFFF); v.w = (short)(u.y >> 16);
+    return v;
+}
+
+// Weights of one wavefront in matrix-core operand form.
+struct Net {
+    bf16x4 a1[4];          // W1 (64 x 16, features 8..15 zero), one tile per 16 hidden units
+    bf16x4 a2[4][4];       // W2 tiles [out][in]
+    bf16x4 a3[4];          // W3 as row 0 of a 16 x 64 matrix
+    float b1[4][4], b2[4][4], w3[4][4];   // per lane: unit 16 t + 4 g + e
+    float b3;
+
+    __device__ void load(const short *__restrict__ wbf, const float *__restrict__ par, int lane) {
+        const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            a1[t] = g < 2 ? ld4(wbf + OFF_W1 + (16 * t + c) * NF + 4 * g) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) a2[t][kt] = ld4(wbf + OFF_W2 + (16 * t + c) * HID + 16 * kt + 4 * g);
+            a3[t] = c == 0 ? ld4(wbf + OFF_W3 + 16 * t + 4 * g) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int u = 16 * t + 4 * g + e;
+                b1[t][e] = par[OFF_B1 + u];
+                b2[t][e] = par[OFF_B2 + u];
+                w3[t][e] = bf16_val(wbf[OFF_W3 + u]);
+            }
+        }
+        b3 = par[OFF_B3];
+    }
+};
+
+// Feature operand of the 16 samples s0 .. s0+15: lane (g, c) holds features
+// 4g .. 4g+3 of sample s0 + c (zero for g >= 2 and past the end).
+__device__ __forceinline__ bf16x4 load_feat(const short *__restrict__ feat, int64_t N, int64_t s0, int lane) {
+    const int g = lane >> 4, c = lane & 15;
+    if (g >= 2 || s0 + c >= N) return bf16x4{0, 0, 0, 0};
+    const uint2 v = *(const uint2 *)(feat + (s0 + c) * NF + 4 * g);
+    bf16x4 r;
+    r.x = (short)(v.x & 0xFFFF); r.y = (short)(v.x >> 16);
+    r.z = (short)(v.y & 0xFFFF); r.w = (short)(v.y >> 16);
+    return r;
+}
+
+// Forward pass of one tile.  h1/h2: bfloat16 activations in B-operand form;
+// m1/m2: bit (4t + e) set when the pre-activation of unit 16t + 4g + e is > 0.
+// Returns the logit (valid in lanes 0..15, sample s0 + lane).
+__device__ __forceinline__ float fwd_tile(const Net &w, bf16x4 x, bf16x4 (&h1)[4], bf16x4 (&h2)[4], uint32_t &m1,
+                                          uint32_t &m2) {
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    m1 = 0;
+    m2 = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f32x4 d = mma(w.a1[t], x, zero);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float z = d[e] + w.b1[t][e];
+            m1 |= (z > 0.f ? 1u : 0u) << (4 * t + e);
+            h1[t][e] = to_bf16(z > 0.f ? z : 0.f);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4 d = zero;
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) d = mma(w.a2[t][kt], h1[kt], d);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float z = d[e] + w.b2[t][e];
+            m2 |= (z > 0.f ? 1u : 0u) << (4 * t + e);
+            h2[t][e] = to_bf16(z > 0.f ? z : 0.f);
+        }
+    }
+    f32x4 d = zero;
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) d = mma(w.a3[kt], h2[kt], d);
+    return d[0] + w.b3;
+}
+
+// Logits of N samples; one wavefront per workgroup, tiles of 16 samples
+// strided over the grid.
+__global__ __launch_bounds__(64) void k_mlp_fwd(const short *__restrict__ wbf, const float *__restrict__ par,
+                                                const short *__restrict__ feat, int64_t N, float *__restrict__ out) {
+    const int lane = (int)threadIdx.x;
+    Net w;
+    w.load(wbf, par, lane);
+    const int64_t tiles = (N + 15) / 16;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t s0 = t * 16;
+        bf16x4 h1[4], h2[4];
+        uint32_t m1, m2;
+        const float z = fwd_tile(w, load_feat(feat, N, s0, lane), h1, h2, m1, m2);
+        if (lane < 16 && s0 + lane < N) out[s0 + lane] = z;
+    }
+}
+
+__device__ __forceinline__ float sum16(float v) {
+    // sum over the 16 lanes of a row (lanes with the same l / 16)
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Gradient of the mean binary cross-entropy over N samples.  Every
+// workgroup (one wavefront) covers the tiles blockIdx.x + k gridDim.x and
+// writes its partial sums (4801 gradient values, then the loss sum) to
+// part[blockIdx.x]; k_mlp_reduce adds the partials in block order.
+__global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, const float *__restrict__ par,
+                                                 const short *__restrict__ feat, const uint8_t *__restrict__ label,
+                                                 int64_t N, float invN, float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) short sA2[HID][16], sH1[HID][16], sA1[HID][16], sF[NF][16];
+    const int lane = (int)threadIdx.x, g = lane >> 4, c = lane & 15;
+    Net w;
+    w.load(wbf, par, lane);
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    f32x4 gW2[4][4], gW1[4];
+    float gW3[4][4], gB2[4][4], gB1[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        gW1[t] = zero;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            gW2[t][u] = zero;
+            gW3[t][u] = 0.f; gB2[t][u] = 0.f; gB1[t][u] = 0.f;
+        }
+    }
+    float gB3 = 0.f, lsum = 0.f;
+    const int64_t tiles = (N + 15) / 16;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t s0 = t * 16;
+        const bf16x4 x = load_feat(feat, N, s0, lane);
+        bf16x4 h1[4], h2[4];
+        uint32_t m1, m2;
+        const float z = fwd_tile(w, x, h1, h2, m1, m2);
+        // dL/dz of sample s0 + lane (lanes 0..15), then broadcast by sample
+        float dz = 0.f;
+        if (lane < 16 && s0 + lane < N) {
+            const float y = label[s0 + lane] ? 1.f : 0.f;
+            const float s = 1.f / (1.f + expf(-z));
+            dz = (s - y) * invN;
+            lsum += fmaxf(z, 0.f) - y * z + log1pf(expf(-fabsf(z)));
+            gB3 += dz;
+        }
+        const float dzc = __shfl(dz, c, 64);
+        bf16x4 d2[4], d1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                gW3[u][e] += dzc * bf16_val(h2[u][e]);
+                const float d = ((m2 >> (4 * u + e)) & 1) ? w.w3[u][e] * dzc : 0.f;
+                gB2[u][e] += d;
+                d2[u][e] = to_bf16(d);
+            }
+        // dH1 = W2^T dA2: A operand W2^T[16 it + c][16 ot + 4g + e] from global (L1/L2 resident)
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            f32x4 acc = zero;
+#pragma unroll
+            for (int ot = 0; ot < 4; ++ot) {
+                bf16x4 a;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[e] = wbf[OFF_W2 + (16 * ot + 4 * g + e) * HID + 16 * it + c];
+                acc = mma(a, d2[ot], acc);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float d = ((m1 >> (4 * it + e)) & 1) ? acc[e] : 0.f;
+                gB1[it][e] += d;
+                d1[it][e] = to_bf16(d);
+            }
+        }
+        // stage (unit x sample) tiles for the reductions over samples
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sA2[16 * u + 4 * g + e][c] = d2[u][e];
+                sH1[16 * u + 4 * g + e][c] = h1[u][e];
+                sA1[16 * u + 4 * g + e][c] = d1[u][e];
+            }
+        if (g < 2)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sF[4 * g + e][c] = x[e];
+        __syncthreads();
+        // dW2[out][in] += sum_s dA2[out][s] a1[in][s];  dW1[out][f] += sum_s dA1[out][s] F[f][s]
+        bf16x4 bh[4];
+#pragma unroll
+        for (int it = 0; it < 4; ++it) bh[it] = ld4(&sH1[16 * it + c][4 * g]);
+        const bf16x4 bf = c < NF ? ld4(&sF[c][4 * g]) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            const bf16x4 a = ld4(&sA2[16 * ot + c][4 * g]);
+#pragma unroll
+            for (int it = 0; it < 4; ++it) gW2[ot][it] = mma(a, bh[it], gW2[ot][it]);
+            gW1[ot] = mma(ld4(&sA1[16 * ot + c][4 * g]), bf, gW1[ot]);
+        }
+        __syncthreads();
+    }
+    float *P = part + (int64_t)blockIdx.x * (NPAR + 1);
+    // matrix-core accumulators: D[i][j] at lane j + 16 floor(i/4), element i mod 4
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int o = 16 * ot + 4 * g + e;
+#pragma unroll
+            for (int it = 0; it < 4; ++it) P[OFF_W2 + o * HID + 16 * it + c] = gW2[ot][it][e];
+            if (c < NF) P[OFF_W1 + o * NF + c] = gW1[ot][e];
+        }
+    // per-lane sums over samples: reduce over the 16 lanes of each row
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float a = sum16(gW3[u][e]), b = sum16(gB2[u][e]), d = sum16(gB1[u][e]);
+            if (c == 0) {
+                P[OFF_W3 + 16 * u + 4 * g + e] = a;
+                P[OFF_B2 + 16 * u + 4 * g + e] = b;
+                P[OFF_B1 + 16 * u + 4 * g + e] = d;
+            }
+        }
+    const float b3 = sum16(gB3), ls = sum16(lsum);
+    if (lane == 0) {
+        P[OFF_B3] = b3;
+        P[NPAR] = ls;
+    }
+}
+
+// grad[i] = sum over blocks of part[b][i] (block order); loss = mean.
+__global__ void k_mlp_reduce(const float *__restrict__ part, int blocks, float invN, float *__restrict__ grad,
+                             float *__restrict__ loss) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > NPAR) return;
+    float s = 0.f;
+    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * (NPAR + 1) + i];
+    if (i < NPAR) grad[i] = s;
+    else if (loss) *loss = s * invN;
+}
+
+// Adam (Kingma & Ba) on the float32 master copy; c1 = 1/(1-b1^t),
+// c2 = 1/(1-b2^t).  Refreshes the bfloat16 copy.
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ grad, float *__restrict__ m,
+                       float *__restrict__ v, short *__restrict__ wbf, float lr, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPAR) return;
+    const float gi = grad[i];
+    const float mi = ADAM_B1 * m[i] + (1.f - ADAM_B1) * gi;
+    const float vi = ADAM_B2 * v[i] + (1.f - ADAM_B2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + ADAM_EPS);
+    p[i] = pi;
+    wbf[i] = to_bf16(pi);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ p, short *__restrict__ wbf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NPAR) wbf[i] = to_bf16(p[i]);
+}
+
+// Bits set in each pool: cnt[q][k] = #{r : bit k of entry (q, r)}.
+__global__ void k_pool_counts(const uint64_t *__restrict__ bits, int P, int m, int n, int nw, int *__restrict__ cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)P * n) return;
+    const int q = (int)(t / n), k = (int)(t % n);
+    int s = 0;
+    for (int r = 0; r < m; ++r) s += (int)((bits[((int64_t)q * m + r) * nw + (k >> 6)] >> (k & 63)) & 1);
+    cnt[t] = s;
+}
+
+// Features of every pooled vector (one workgroup per entry (q, r)).  The
+// local field h_k = W_kk + 2 sum_{j != k} W_kj x_j is accumulated in LDS over
+// the set bits j of the entry (the packed W has a zero diagonal).
+template <typename WT>
+__global__ __launch_bounds__(256) void k_features(const WT *__restrict__ W, const int *__restrict__ diag,
+                                                  const int64_t *__restrict__ rowabs, int64_t ld, int n, int nw,
+                                                  int64_t bound, const uint64_t *__restrict__ bits, int m,
+                                                  const int *__restrict__ cnt, short *__restrict__ feat) {
+    __shared__ int h[4096];
+    const int cell = blockIdx.x, q = cell / m, r = cell % m;
+    const uint64_t *x = bits + (int64_t)cell * nw;
+    const uint64_t *best = bits + (int64_t)q * m * nw;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] = diag[k];
+    for (int wd = 0; wd < nw; ++wd) {
+        uint64_t word = x[wd];
+        if (wd == nw - 1 && (n & 63)) word &= (1ull << (n & 63)) - 1;   // bits >= n are not part of X
+        while (word) {
+            const int j = wd * 64 + __builtin_ctzll(word);
+            word &= word - 1;
+            const WT *row = W + (int64_t)j * ld;
+            for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] += 2 * (int)row[k];
+        }
+    }
+    __syncthreads();
+    const float fB = (float)bound, fm = (float)m;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const int xk = (int)((x[k >> 6] >> (k & 63)) & 1), bk = (int)((best[k >> 6] >> (k & 63)) & 1);
+        const int delta = (1 - 2 * xk) * h[k];
+        float f[NF];
+        f[0] = (float)delta / fB;
+        f[1] = (float)(2 * xk - 1);
+        f[2] = (float)diag[k] / fB;
+        f[3] = (float)rowabs[k] / fB;
+        f[4] = 2.0f * ((float)cnt[(int64_t)q * n + k] / fm) - 1.0f;
+        f[5] = f[1] * f[4];
+        f[6] = (float)(2 * bk - 1);
+        f[7] = (float)r / fm;
+        uint4 o;
+        o.x = (uint32_t)(uint16_t)to_bf16(f[0]) | (uint32_t)(uint16_t)to_bf16(f[1]) << 16;
+        o.y = (uint32_t)(uint16_t)to_bf16(f[2]) | (uint32_t)(uint16_t)to_bf16(f[3]) << 16;
+        o.z = (uint32_t)(uint16_t)to_bf16(f[4]) | (uint32_t)(uint16_t)to_bf16(f[5]) << 16;
+        o.w = (uint32_t)(uint16_t)to_bf16(f[6]) | (uint32_t)(uint16_t)to_bf16(f[7]) << 16;
+        *(uint4 *)(feat + ((int64_t)cell * n + k) * NF) = o;
+    }
+}
+
+// label[e][k] = 1 when bit k of vector e differs from the reference vector.
+__global__ void k_labels(const uint64_t *__restrict__ bits, int64_t count, int n, int nw,
+                         const uint64_t *__restrict__ ref, uint8_t *__restrict__ label) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count * n) return;
+    const int64_t e = t / n;
+    const int k = (int)(t % n);
+    label[t] = (uint8_t)(((bits[e * nw + (k >> 6)] ^ ref[k >> 6]) >> (k & 63)) & 1);
+}
+
+__global__ void k_apply_op(int op, int n, int nw, int count, const uint64_t *__restrict__ parent,
+                           const float *__restrict__ logits, uint64_t seed, uint32_t rd, uint32_t inst0,
+                           uint64_t *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)count * nw) return;
+    const int i = (int)(t / nw), w = (int)(t % nw);
+    out[t] = mlp_op_word(op, parent[t], logits + (int64_t)i * n, n, w, seed, rd, inst0 + (uint32_t)i);
+}
+
+}  // namespace dabs
+
+using namespace dabs;
+
+struct dabs_mlp {
+    float *par, *m, *v, *grad, *loss, *part;
+    short *wbf;
+    int step;
+};
+
+namespace dabs {
+
+int mlp_pool_logits(const dabs_problem *p, const dabs_mlp *net, const uint64_t *pool_bits, int P, int m,
+                    int *cnt, short *feat, float *logits, hipStream_t st) {
+    const int n = p->n, nw = (n + 63) / 64;
+    const int64_t pn = (int64_t)P * n;
+    hipLaunchKernelGGL(k_pool_counts, dim3((unsigned)((pn + 255) / 256)), dim3(256), 0, st, pool_bits, P, m, n, nw,
+                       cnt);
+    HIP_OK(hipGetLastError());
+    if (p->wtype == DABS_W_I16)
+        hipLaunchKernelGGL(k_features<int16_t>, dim3(P * m), dim3(256), 0, st, (const int16_t *)p->W, p->diag,
+                           p->rowabs, p->ld, n, nw, p->bound, pool_bits, m, cnt, feat);
+    else
+        hipLaunchKernelGGL(k_features<int32_t>, dim3(P * m), dim3(256), 0, st, (const int32_t *)p->W, p->diag,
+                           p->rowabs, p->ld, n, nw, p->bound, pool_bits, m, cnt, feat);
+    HIP_OK(hipGetLastError());
+    if (net && logits) {
+        const int64_t N = (int64_t)P * m * n, tiles = (N + 15) / 16;
+        const unsigned blocks = (unsigned)(tiles < 8192 ? tiles : 8192);
+        hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks), dim3(64), 0, st, net->wbf, net->par, feat, N, logits);
+        HIP_OK(hipGetLastError());
+    }
+    return DABS_OK;
+}
+
+}  // namespace dabs
+
+extern "C" {
+
+int dabs_mlp_create(const float *params_host, dabs_mlp **out) {
+    if (!out) return dabs_fail(DABS_E_INVALID, "null output");
+    dabs_mlp *s = new dabs_mlp();
+    const size_t fb = sizeof(float) * NPAR;
+    bool ok = hipMalloc(&s->par, fb) == hipSuccess && hipMalloc(&s->m, fb) == hipSuccess &&
+              hipMalloc(&s->v, fb) == hipSuccess && hipMalloc(&s->grad, fb) == hipSuccess &&
+              hipMalloc(&s->loss, sizeof(float)) == hipSuccess && hipMalloc(&s->wbf, sizeof(short) * NPAR) == hipSuccess &&
+              hipMalloc(&s->part, sizeof(float) * (NPAR + 1) * GRAD_BLOCKS_MAX) == hipSuccess;
+    if (ok) {
+        ok = hipMemset(s->m, 0, fb) == hipSuccess && hipMemset(s->v, 0, fb) == hipSuccess &&
+             hipMemset(s->grad, 0, fb) == hipSuccess;
+        if (params_host) ok = ok && hipMemcpy(s->par, params_host, fb, hipMemcpyHostToDevice) == hipSuccess;
+        else ok = ok && hipMemset(s->par, 0, fb) == hipSuccess;
+    }
+    if (ok) {
+        hipLaunchKernelGGL(k_to_bf16, dim3((NPAR + 255) / 256), dim3(256), 0, 0, s->par, s->wbf);
+        ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        dabs_mlp_destroy(s);
+        return dabs_fail(DABS_E_NOMEM, "MLP allocation / upload failed");
+    }
+    *out = s;
+    return DABS_OK;
+}
+
+int dabs_mlp_destroy(dabs_mlp *s) {
+    if (!s) return DABS_OK;
+    void *ptrs[] = {s->par, s->m, s->v, s->grad, s->loss, s->wbf, s->part};
+    for (void *p : ptrs) (void)hipFree(p);
+    delete s;
+    return DABS_OK;
+}
+
+int dabs_mlp_params(const dabs_mlp *s, float *params_dev, void *stream) {
+    if (!s || !params_dev) return dabs_fail(DABS_E_INVALID, "null argument");
+    HIP_OK(hipMemcpyAsync(params_dev, s->par, sizeof(float) * NPAR, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return DABS_OK;
+}
+
+int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev, int32_t npools, int32_t capacity,
+                           uint16_t *feat_dev, void *stream) {
+    if (!p || !pool_bits_dev || !feat_dev) return dabs_fail(DABS_E_INVALID, "null argument");
+    if (npools < 1 || capacity < 1) return dabs_fail(DABS_E_INVALID, "bad pool shape");
+    if (p->n > 4096) return dabs_fail(DABS_E_UNSUPPORTED, "features need n <= 4096");
+    int *cnt = nullptr;
+    HIP_OK(hipMalloc((void **)&cnt, sizeof(int) * (size_t)npools * p->n));
+    int r = mlp_pool_logits(p, nullptr, pool_bits_dev, npools, capacity, cnt, (short *)feat_dev, nullptr,
+                            (hipStream_t)stream);
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && r == DABS_OK)
+        r = dabs_fail(DABS_E_HIP, "feature kernels failed");
+    (void)hipFree(cnt);
+    return r;
+}
+
+int dabs_mlp_labels(const dabs_problem *p, const uint64_t *bits_dev, int64_t count, const uint64_t *ref_dev,
+                    uint8_t *labels_dev, void *stream) {
+    if (!p || !bits_dev || !ref_dev || !labels_dev || count < 0) return dabs_fail(DABS_E_INVALID, "bad argument");
+    const int64_t tot = count * p->n;
+    if (tot == 0) return DABS_OK;
+    hipLaunchKernelGGL(k_labels, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, (hipStream_t)stream, bits_dev,
+                       count, p->n, (p->n + 63) / 64, ref_dev, labels_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+int dabs_mlp_forward(const dabs_mlp *s, int64_t count, const uint16_t *feat_dev, float *logits_dev, void *stream) {
+    if (!s || !feat_dev || !logits_dev || count < 0) return dabs_fail(DABS_E_INVALID, "bad argument");
+    if (count == 0) return DABS_OK;
+    const int64_t tiles = (count + 15) / 16;
+    const unsigned blocks = (unsigned)(tiles < 8192 ? tiles : 8192);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks), dim3(64), 0, (hipStream_t)stream, s->wbf, s->par,
+                       (const short *)feat_dev, count, logits_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+int dabs_mlp_grad(dabs_mlp *s, int64_t count, const uint16_t *feat_dev, const uint8_t *labels_dev, float *grad_dev,
+                  float *loss_dev, void *stream) {
+    if (!s || !feat_dev || !labels_dev || count < 1) return dabs_fail(DABS_E_INVALID, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t tiles = (count + 15) / 16;
+    const int blocks = (int)(tiles < GRAD_BLOCKS_MAX ? tiles : GRAD_BLOCKS_MAX);
+    const float invN = (float)(1.0 / (double)count);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(64), 0, st, s->wbf, s->par, (const short *)feat_dev, labels_dev,
+                       count, invN, s->part);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NPAR + 1 + 255) / 256), dim3(256), 0, st, s->part, blocks, invN, s->grad,
+                       s->loss);
+    HIP_OK(hipGetLastError());
+    if (grad_dev) HIP_OK(hipMemcpyAsync(grad_dev, s->grad, sizeof(float) * NPAR, hipMemcpyDeviceToDevice, st));
+    if (loss_dev) HIP_OK(hipMemcpyAsync(loss_dev, s->loss, sizeof(float), hipMemcpyDeviceToDevice, st));
+    return DABS_OK;
+}
+
+int dabs_mlp_adam(dabs_mlp *s, float lr, void *stream) {
+    if (!s || !(lr > 0.f)) return dabs_fail(DABS_E_INVALID, "bad argument");
+    s->step++;
+    const double c1 = 1.0 / (1.0 - pow((double)ADAM_B1, s->step)), c2 = 1.0 / (1.0 - pow((double)ADAM_B2, s->step));
+    hipLaunchKernelGGL(k_adam, dim3((NPAR + 255) / 256), dim3(256), 0, (hipStream_t)stream, s->par, s->grad, s->m,
+                       s->v, s->wbf, lr, (float)c1, (float)c2);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+int dabs_mlp_train_step(dabs_mlp *s, int64_t count, const uint16_t *feat_dev, const uint8_t *labels_dev, float lr,
+                        float *loss_dev, void *stream) {
+    const int r = dabs_mlp_grad(s, count, feat_dev, labels_dev, nullptr, loss_dev, stream);
+    if (r != DABS_OK) return r;
+    return dabs_mlp_adam(s, lr, stream);
+}
+
+int dabs_mlp_apply_op(int32_t op, int32_t n, int32_t count, const uint64_t *parent_dev, const float *logits_dev,
+                      uint64_t seed, uint32_t round, uint32_t inst0, uint64_t *out_dev, void *stream) {
+    if (op != DABS_OP_MLP_SEED && op != DABS_OP_MLP_MUTATE) return dabs_fail(DABS_E_INVALID, "not an MLP operation");
+    if (n < 1 || count < 0 || !parent_dev || !logits_dev || !out_dev) return dabs_fail(DABS_E_INVALID, "bad argument");
+    const int nw = (n + 63) / 64;
+    const int64_t tot = (int64_t)count * nw;
+    if (tot == 0) return DABS_OK;
+    hipLaunchKernelGGL(k_apply_op, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, (hipStream_t)stream, op, n, nw,
+                       count, parent_dev, logits_dev, seed, round, inst0, out_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+}  // extern "C"
