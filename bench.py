@@ -39,6 +39,46 @@ SEED = 0
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_items_maxcut800_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources and headers the search kernels are built from."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2207_03069_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "include", "dabs.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the batch-search kernel from the committed
+    rocprofv3 counter summary, or None when the kernels changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain device copy of 256 MiB (for scaling FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    a = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4}))
+
+
 def workload():
     W, edges, w = inputs.maxcut_instance(N_BITS, P_EDGE, seed=SEED)
     T, Bn = round(S_FACTOR * N_BITS), round(B_FACTOR * N_BITS)
@@ -70,6 +110,154 @@ def cpu_baseline(W, T, Bn):
                       (cores, flips, dt)}
 
 
+def _first_hits(solver_run, progress, rounds_cap, nprob, dev):
+    """Runs one round at a time until every problem's first hit is recorded
+    (or the cap); returns per-problem hit seconds (None = not reached) and the
+    rounds run."""
+    import torch
+    prog = torch.zeros((nprob, 2), dtype=torch.int64, device=dev)
+    hits = [None] * nprob
+    r = 0
+    for r in range(1, rounds_cap + 1):
+        solver_run()
+        progress(prog)
+        torch.cuda.synchronize()
+        h = prog[:, 0].cpu().numpy()
+        if (h >= 0).all():
+            break
+    h = prog[:, 0].cpu().numpy()
+    return [float(v) / 1e8 if v >= 0 else None for v in h], r
+
+
+def learned_vs_plain(dev, n=2048, instances=1024, ref_rounds=8, cap=24):
+    """Time to target of the plain DABS loop and of the loop with the learned
+    operations on a dense n = 2048 int16 QUBO (U[-1000, 1000], seed 0), after
+    training the network on pool solutions of a plain run on another problem
+    of the same family (seed 1).  Target: the best energy of a plain reference
+    run with another seed after ref_rounds rounds."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    from paper_2207_03069_amd import train
+    T, Bn = round(S_FACTOR * n), n                      # s = 0.1, b = 1
+
+    def params(seed, ops=tuple(range(8))):
+        return dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=seed, capacity=CAPACITY, npools=NPOOLS, ops=ops)
+    t0 = time.perf_counter()
+    ptr = dabs.dabs_problem_create(torch.from_numpy(inputs.dense_qubo(n, -1000, 1000, 1)).to(dev))
+    feats, labels, _ = train.collect(ptr, params(101), instances=instances, rounds=2 * ref_rounds, every=2)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    net, hist = train.fit(feats, labels, epochs=2, batch=1 << 16, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    nsamp = int(feats.shape[0])
+    del feats, labels, ptr
+    prob = dabs.dabs_problem_create(torch.from_numpy(inputs.dense_qubo(n, -1000, 1000, 0)).to(dev))
+    ref = dabs.dabs_solver_create(prob, params(999), instances)
+    dabs.dabs_solver_run(ref, ref_rounds)
+    prog = torch.zeros(2, dtype=torch.int64, device=dev)
+    dabs.dabs_solver_progress(ref, prog)
+    torch.cuda.synchronize()
+    target = int(prog[1].item())
+    del ref
+    tgt = torch.tensor([target], dtype=torch.int64, device=dev)
+    res = {}
+    for name, ops in (("plain", tuple(range(8))), ("learned", tuple(range(10)))):
+        hits, rounds = [], []
+        for seed in (1, 2, 3, 4, 5):
+            s = dabs.dabs_solver_create(prob, params(seed, ops), instances)
+            if name == "learned":
+                dabs.dabs_solver_set_mlp(s, net)
+            calls = [0]
+
+            def run_one(s=s):
+                # the first call arms the target and starts the device clock
+                dabs.dabs_solver_run(s, 1, tgt if calls[0] == 0 else None)
+                calls[0] += 1
+            h, r = _first_hits(run_one, lambda o, s=s: dabs.dabs_solver_progress(s, o), cap, 1, dev)
+            hits.append(h[0])
+            rounds.append(r if h[0] is not None else None)
+            del s
+        ok = [x for x in hits if x is not None]
+        res[name] = {"seconds_per_seed": hits, "rounds_per_seed": rounds,
+                     "median_s": float(np.median([x if x is not None else np.inf for x in hits])),
+                     "reached": len(ok), "runs": len(hits)}
+    return {"problem": "dense int16 QUBO n=%d U[-1000,1000] seed 0, %d instances, 8 pools x 100, s=0.1 b=1"
+                       % (n, instances),
+            "target_e": target, "target_from": "plain run, seed 999, %d rounds" % ref_rounds, "round_cap": cap,
+            "training": {"problem": "same family, seed 1", "pool_solutions": nsamp // n, "samples": nsamp,
+                         "epochs": len(hist), "loss_per_epoch": hist, "collect_s": t_collect, "train_s": t_train},
+            "plain": res["plain"], "learned": res["learned"]}
+
+
+def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
+    """The many-problem workload: 256 dense int16 QUBOs, n log-uniform in
+    [256, 4096), U[-1000, 1000].  Target of each problem: its best energy after
+    ref_rounds rounds of a reference run with other seeds.  Batched: all
+    problems in one graph-replayed round; single: one solver per problem, run
+    one after another (one launch sequence per problem).  Same seeds, so both
+    follow the same trajectories; the comparison is the time to the targets."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    t0 = time.perf_counter()
+    Ws = inputs.batched_problems(nprob, seed=0)
+    probs = [dabs.dabs_problem_create(torch.from_numpy(W).to(dev)) for W in Ws]
+    sizes = [int(W.shape[0]) for W in Ws]
+    del Ws
+    t_load = time.perf_counter() - t0
+
+    def params(seed0):
+        return [dabs.ga_params(T=max(1, round(0.1 * n)), Bn=n, tau=TAU, seed=seed0 + p, capacity=16, npools=2)
+                for p, n in enumerate(sizes)]
+    ref = dabs.dabs_batched_create(probs, params(50000), [inst] * nprob)
+    dabs.dabs_batched_run(ref, ref_rounds, None, use_graph=True)
+    prog = torch.zeros((nprob, 2), dtype=torch.int64, device=dev)
+    dabs.dabs_batched_progress(ref, prog)
+    torch.cuda.synchronize()
+    targets = prog[:, 1].clone()
+    del ref
+    # batched
+    b = dabs.dabs_batched_create(probs, params(1), [inst] * nprob)
+    calls = [0]
+
+    def run_b():
+        dabs.dabs_batched_run(b, 1, targets if calls[0] == 0 else None, use_graph=True)
+        calls[0] += 1
+    tw = time.perf_counter()
+    hb, rb = _first_hits(run_b, lambda o: dabs.dabs_batched_progress(b, o), cap, nprob, dev)
+    wall_b = time.perf_counter() - tw
+    del b
+    # one problem at a time
+    hs, wall_s = [], 0.0
+    gp = params(1)
+    for p in range(nprob):
+        s = dabs.dabs_solver_create(probs[p], gp[p], inst)
+        tp = targets[p:p + 1].clone()
+        c = [0]
+
+        def run_s(s=s, tp=tp, c=c):
+            dabs.dabs_solver_run(s, 1, tp if c[0] == 0 else None)
+            c[0] += 1
+        tw = time.perf_counter()
+        h, _ = _first_hits(run_s, lambda o, s=s: dabs.dabs_solver_progress(s, o), cap, 1, dev)
+        wall_s += time.perf_counter() - tw
+        hs.append(h[0])
+        del s
+
+    def summary(h):
+        ok = [x for x in h if x is not None]
+        return {"reached": len(ok), "median_s": float(np.median(ok)) if ok else None,
+                "max_s": float(max(ok)) if ok else None, "sum_s": float(sum(ok))}
+    sb, ss = summary(hb), summary(hs)
+    return {"problems": nprob, "instances_per_problem": inst, "n_min": min(sizes), "n_max": max(sizes),
+            "targets": "best energy per problem after %d rounds of a reference run (other seeds)" % ref_rounds,
+            "round_cap": cap, "load_s": t_load,
+            "batched": dict(sb, time_all_reached_s=sb["max_s"], wall_s=wall_b, rounds=rb),
+            "single": dict(ss, time_all_reached_s=ss["sum_s"], wall_s=wall_s,
+                           note="problems run one after another; all reached after the sum of their times")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +265,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run a 256 MiB device copy")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -123,7 +317,8 @@ def main():
     ops_per_flip = 2 * N_BITS
     achieved_ops = walk_flips * ops_per_flip / walk_s
     roofline = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s (int32 lane-ops)", "frac": achieved_ops / VALU_PEAK_OPS, "traffic": None,
+                "unit": "Tops/s (int32 lane-ops)", "frac": achieved_ops / VALU_PEAK_OPS, "traffic": measured_traffic(),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, calibrated by a copy)",
                 "kernel": "k_walk_items (batch search, one wavefront per instance)", "launches": launches,
                 "avg_launch_ms": walk_ms / max(launches, 1),
                 "w_row_bytes_per_s": walk_flips * bytes_per_flip / walk_s / 1e9,
@@ -131,20 +326,29 @@ def main():
 
     tts = None
     if not args.no_tts:
+        # rerun with the same seeds until the best energy of the timed run is
+        # reached; the first call arms the target and starts the device clock
         s2 = dabs.dabs_solver_create(prob, g, INSTANCES)
         tgt = torch.tensor([best_e], dtype=torch.int64, device=dev)
-        hit = -1
+        calls = [0]
+
+        def run_one():
+            dabs.dabs_solver_run(s2, 1, tgt if calls[0] == 0 else None)
+            calls[0] += 1
         t1 = time.perf_counter()
-        for _ in range(args.warmup + args.steps):
-            dabs.dabs_solver_run(s2, ROUNDS_PER_STEP, tgt)
-            dabs.dabs_solver_progress(s2, prog)
-            torch.cuda.synchronize()
-            if int(prog[0].item()) >= 0:
-                break
-        wall = time.perf_counter() - t1
-        hit = int(prog[0].item())
-        tts = {"target_e": best_e, "seconds": hit / 1e8 if hit >= 0 else None, "wall_s_incl_polling": wall,
+        h, r = _first_hits(run_one, lambda o: dabs.dabs_solver_progress(s2, o),
+                           (args.warmup + args.steps) * ROUNDS_PER_STEP, 1, dev)
+        tts = {"target_e": best_e, "seconds": h[0], "rounds": r, "wall_s_incl_polling": time.perf_counter() - t1,
                "note": "first E(BEST) <= target in a rerun with the same seeds; device clock 100 MHz"}
+        del s2
+    learned = None
+    if not args.no_learned:
+        print("bench: learned vs plain ...", file=sys.stderr, flush=True)
+        learned = learned_vs_plain(dev)
+    batched = None
+    if not args.no_batched:
+        print("bench: batched vs one problem at a time ...", file=sys.stderr, flush=True)
+        batched = batched_vs_single(dev)
 
     out = {
         "metric": "flips_per_sec_per_gpu", "value": flips / dt, "unit": "flips/s",
@@ -157,6 +361,8 @@ def main():
                    "tau": TAU, "npools": NPOOLS, "capacity": CAPACITY, "flips_per_step": flips / args.steps},
         "best_energy": best_e,
         "time_to_target": tts,
+        "time_to_target_learned_vs_plain": learned,
+        "time_to_target_batched_vs_single": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -202,9 +202,11 @@ int dabs_solver_destroy(dabs_solver *s);
  * Section III-B): every instance draws a target from its pool (adaptive
  * op/algorithm choice, rank selection, genetic operation), runs one batch
  * search, and the packets are inserted into the pools in instance order.
- * If target_e is not NULL, the device records the first time (in ticks of
- * the 100 MHz device clock, counted from the start of this call's first
- * round) at which some instance's E(BEST) <= *target_e.
+ * target_e (device, int64): if not NULL, arms time-to-target: the clock
+ * restarts at the start of this call and the device records the first time
+ * (ticks of the 100 MHz device clock) at which some instance's
+ * E(BEST) <= *target_e.  NULL continues the last armed run: same target,
+ * same clock, same first-hit record (no target if none was ever armed).
  */
 int dabs_solver_run(dabs_solver *s, int32_t rounds, const int64_t *target_e, void *stream);
 
@@ -259,9 +261,9 @@ int dabs_batched_destroy(dabs_batched *b);
 /*
  * Run `rounds` rounds.  use_graph != 0 captures one round into a HIP graph
  * on first use and replays it (ignored when the batch times its kernels).
- * target_e_dev: nullable [nprob] int64 time-to-target energies; the first
- * hit of each problem is recorded in 100 MHz device ticks from the start of
- * this call.
+ * target_e_dev: nullable [nprob] int64 time-to-target energies; non-NULL
+ * arms them (clock restarts, first hits cleared), NULL continues the last
+ * armed run; first hits are in 100 MHz device ticks from the arming call.
  */
 int dabs_batched_run(dabs_batched *b, int32_t rounds, const int64_t *target_e_dev, int32_t use_graph,
                      void *stream);

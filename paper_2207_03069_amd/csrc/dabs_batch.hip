@@ -292,6 +292,7 @@ struct dabs_batched {
     hipGraphExec_t exec;
     bool graph_ready;
     int ttt;                           // time-to-target armed for the captured round
+    bool armed;                        // a run armed targets; later runs continue its clock
     // optional timing of the batch-search kernels (DABS_SOLVER_TIME_WALK)
     bool timed;
     static constexpr int NEV = 256;
@@ -503,9 +504,13 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
 static int batched_run(dabs_batched *s, int rounds, const int64_t *target_e, int use_graph, hipStream_t st) {
     if (rounds < 0) return dabs_fail(DABS_E_INVALID, "rounds < 0");
     if (s->mlp_ops && !s->mlp) return dabs_fail(DABS_E_INVALID, "MLP operations enabled but no network attached");
-    const int ttt = target_e ? 1 : 0;
-    hipLaunchKernelGGL(k_run_begin, dim3((s->nprob + 255) / 256), dim3(256), 0, st, s->d, s->nprob, target_e);
-    HIP_OK(hipGetLastError());
+    if (target_e) {
+        // arm: clock, targets and first-hit records restart here
+        hipLaunchKernelGGL(k_run_begin, dim3((s->nprob + 255) / 256), dim3(256), 0, st, s->d, s->nprob, target_e);
+        HIP_OK(hipGetLastError());
+        s->armed = true;
+    }
+    const int ttt = s->armed ? 1 : 0;
     if (!use_graph || s->timed) {
         for (int r = 0; r < rounds; ++r) {
             const int c = enqueue_round(s, st, ttt, false);
