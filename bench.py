@@ -129,7 +129,7 @@ def _first_hits(solver_run, progress, rounds_cap, nprob, dev):
     return [float(v) / 1e8 if v >= 0 else None for v in h], r
 
 
-def learned_vs_plain(dev, n=2048, instances=1024, ref_rounds=8, cap=24):
+def learned_vs_plain(dev, n=2048, instances=512, ref_rounds=32, cap=96):
     """Time to target of the plain DABS loop and of the loop with the learned
     operations on a dense n = 2048 int16 QUBO (U[-1000, 1000], seed 0), after
     training the network on pool solutions of a plain run on another problem
@@ -144,7 +144,7 @@ def learned_vs_plain(dev, n=2048, instances=1024, ref_rounds=8, cap=24):
         return dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=seed, capacity=CAPACITY, npools=NPOOLS, ops=ops)
     t0 = time.perf_counter()
     ptr = dabs.dabs_problem_create(torch.from_numpy(inputs.dense_qubo(n, -1000, 1000, 1)).to(dev))
-    feats, labels, _ = train.collect(ptr, params(101), instances=instances, rounds=2 * ref_rounds, every=2)
+    feats, labels, _ = train.collect(ptr, params(101), instances=instances, rounds=125, every=1)  # 10^5 pooled vectors
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
     t1 = time.perf_counter()
@@ -155,6 +155,7 @@ def learned_vs_plain(dev, n=2048, instances=1024, ref_rounds=8, cap=24):
     del feats, labels, ptr
     prob = dabs.dabs_problem_create(torch.from_numpy(inputs.dense_qubo(n, -1000, 1000, 0)).to(dev))
     ref = dabs.dabs_solver_create(prob, params(999), instances)
+    dabs.dabs_solver_autotune(ref)
     dabs.dabs_solver_run(ref, ref_rounds)
     prog = torch.zeros(2, dtype=torch.int64, device=dev)
     dabs.dabs_solver_progress(ref, prog)
@@ -169,6 +170,7 @@ def learned_vs_plain(dev, n=2048, instances=1024, ref_rounds=8, cap=24):
             s = dabs.dabs_solver_create(prob, params(seed, ops), instances)
             if name == "learned":
                 dabs.dabs_solver_set_mlp(s, net)
+            dabs.dabs_solver_autotune(s)
             calls = [0]
 
             def run_one(s=s):
@@ -219,6 +221,8 @@ def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
     del ref
     # batched
     b = dabs.dabs_batched_create(probs, params(1), [inst] * nprob)
+    tune_ms, tune_choice = dabs.dabs_batched_autotune(b)
+    classes = dabs.dabs_batched_classes(b)
     calls = [0]
 
     def run_b():
@@ -253,7 +257,9 @@ def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
     return {"problems": nprob, "instances_per_problem": inst, "n_min": min(sizes), "n_max": max(sizes),
             "targets": "best energy per problem after %d rounds of a reference run (other seeds)" % ref_rounds,
             "round_cap": cap, "load_s": t_load,
-            "batched": dict(sb, time_all_reached_s=sb["max_s"], wall_s=wall_b, rounds=rb),
+            "batched": dict(sb, time_all_reached_s=sb["max_s"], wall_s=wall_b, rounds=rb,
+                            autotune=[{"wtype": c[0], "slots": c[1], "items": c[2], "variant_ms": m, "chosen": c[3]}
+                                      for c, m in zip(classes, tune_ms)]),
             "single": dict(ss, time_all_reached_s=ss["sum_s"], wall_s=wall_s,
                            note="problems run one after another; all reached after the sum of their times")}
 
@@ -291,6 +297,7 @@ def main():
     for _ in range(args.warmup):
         dabs.dabs_solver_run(solver, ROUNDS_PER_STEP)
     torch.cuda.synchronize()
+    tune_ms, tune_choice = dabs.dabs_solver_autotune(solver)
     dabs.dabs_solver_timing(solver, reset=True)
     tot = torch.zeros(1, dtype=torch.int64, device=dev)
     dabs.dabs_solver_state(solver, total_flips=tot)
@@ -320,6 +327,8 @@ def main():
                 "unit": "Tops/s (int32 lane-ops)", "frac": achieved_ops / VALU_PEAK_OPS, "traffic": measured_traffic(),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, calibrated by a copy)",
                 "kernel": "k_walk_items (batch search, one wavefront per instance)", "launches": launches,
+                "autotune": {"variant_ms": tune_ms[0], "chosen": tune_choice[0],
+                             "variants": ["<=128 VGPRs (4 waves/SIMD)", "uncapped registers"]},
                 "avg_launch_ms": walk_ms / max(launches, 1),
                 "w_row_bytes_per_s": walk_flips * bytes_per_flip / walk_s / 1e9,
                 "w_row_unit": "GB/s of W rows (L2-resident, 1.28 MB)"}

@@ -280,6 +280,21 @@ int dabs_batched_flips(const dabs_batched *b, int64_t *total_flips_dev, void *st
 int dabs_batched_timing(dabs_batched *b, double *out_host, int32_t reset);
 
 /*
+ * Autotuner: for every size class of the batch (weight type x slot count),
+ * times each compiled variant of the batch-search kernel (register cap for
+ * 4 waves per SIMD, or uncapped) on the batch's own next-round items and keeps
+ * the fastest for the following rounds.  The instance state is saved and
+ * restored, so results are unchanged (only speed).  Synchronises the stream.
+ *   ms_out     nullable [nclasses][2] milliseconds per variant
+ *   choice_out nullable [nclasses] chosen variant
+ * dabs_batched_classes fills [min(nclasses, cap)][4] = (wtype, slots, items,
+ * variant) and returns nclasses.
+ */
+int dabs_batched_autotune(dabs_batched *b, double *ms_out, int32_t *choice_out, void *stream);
+int dabs_solver_autotune(dabs_solver *s, double *ms_out, int32_t *choice_out, void *stream);
+int dabs_batched_classes(const dabs_batched *b, int32_t *wtype_slots_count_variant, int32_t cap);
+
+/*
  * Learned proposal.  Not in the paper: a small network that scores every bit
  * of a pooled vector and two genetic operations that use the scores; the
  * exact search of Section III stays the judge (energies are never

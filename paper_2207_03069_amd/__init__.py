@@ -93,6 +93,9 @@ _SIGS = {
     "dabs_mlp_apply_op": ([C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_uint64, C.c_uint32, C.c_uint32, _P, _P],
                           C.c_int),
     "dabs_solver_set_mlp": ([_P, _P], C.c_int),
+    "dabs_batched_autotune": ([_P, _P, _P, _P], C.c_int),
+    "dabs_solver_autotune": ([_P, _P, _P, _P], C.c_int),
+    "dabs_batched_classes": ([_P, _P, C.c_int32], C.c_int),
     "dabs_batched_set_mlp": ([_P, _P], C.c_int),
 }
 
@@ -393,3 +396,30 @@ def dabs_solver_set_mlp(s: Solver, m):
 def dabs_batched_set_mlp(b: Batched, m):
     _check(lib().dabs_batched_set_mlp(b.handle, None if m is None else m.handle))
     b.mlp = m
+
+
+# ------------------------------------------------------------------ autotuner
+def dabs_batched_classes(b: Batched):
+    """[(wtype, slots, items, variant)] of the batch's size classes."""
+    nc = lib().dabs_batched_classes(b.handle, None, 0)
+    if nc < 0:
+        _check(nc)
+    out = (C.c_int32 * (4 * max(nc, 1)))()
+    lib().dabs_batched_classes(b.handle, C.cast(out, C.c_void_p), nc)
+    return [tuple(out[4 * c:4 * c + 4]) for c in range(nc)]
+
+
+def dabs_batched_autotune(b: Batched, stream=None):
+    """Returns (milliseconds [class][variant], chosen variant per class)."""
+    nc = len(dabs_batched_classes(b))
+    ms = (C.c_double * (2 * nc))()
+    ch = (C.c_int32 * nc)()
+    _check(lib().dabs_batched_autotune(b.handle, C.cast(ms, C.c_void_p), C.cast(ch, C.c_void_p), _stream(stream)))
+    return [[ms[2 * c], ms[2 * c + 1]] for c in range(nc)], list(ch)
+
+
+def dabs_solver_autotune(s: Solver, stream=None):
+    ms = (C.c_double * 2)()
+    ch = (C.c_int32 * 1)()
+    _check(lib().dabs_solver_autotune(s.handle, C.cast(ms, C.c_void_p), C.cast(ch, C.c_void_p), _stream(stream)))
+    return [[ms[0], ms[1]]], list(ch)

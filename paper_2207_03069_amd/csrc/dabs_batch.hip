@@ -283,7 +283,7 @@ struct dabs_batched {
     int2 *items;                       // device, grouped by class
     int2 *pool_list;                   // device, (problem, pool)
     int npool_list;
-    struct Cls { int wtype, slots, begin, count; };
+    struct Cls { int wtype, slots, begin, count, variant; };
     std::vector<Cls> classes;
     hipStream_t side[MAX_CLASSES];
     hipEvent_t fork, join[MAX_CLASSES];
@@ -390,7 +390,8 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
             const ProbDesc &A = s->hdesc[a], &B = s->hdesc[b];
             return (int64_t)A.n * (A.g.Bn + A.n) > (int64_t)B.n * (B.g.Bn + B.n);
         });
-        dabs_batched::Cls c = {k.first, k.second, (int)items.size(), 0};
+        // default variant until tuned: measured faster uncapped from 4 slots up
+        dabs_batched::Cls c = {k.first, k.second, (int)items.size(), 0, k.second >= 4 ? 1 : 0};
         for (int p : ps)
             for (int i = 0; i < s->hdesc[p].instances; ++i) items.push_back(make_int2(p, i));
         c.count = (int)items.size() - c.begin;
@@ -486,7 +487,7 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
         a.items = s->items + s->classes[c].begin;
         a.nitems = s->classes[c].count;
         a.ttt = ttt;
-        HIP_OK(launch_walk_items(s->classes[c].wtype, s->classes[c].slots, a, cs));
+        HIP_OK(launch_walk_items(s->classes[c].wtype, s->classes[c].slots, s->classes[c].variant, a, cs));
         if (nc > 1) HIP_OK(hipEventRecord(s->join[c], cs));
     }
     for (int c = 0; c < nc && nc > 1; ++c) HIP_OK(hipStreamWaitEvent(st, s->join[c], 0));
@@ -628,6 +629,92 @@ int dabs_batched_timing(dabs_batched *s, double *out, int32_t reset) {
     return DABS_OK;
 }
 
+// Per size class, times every compiled variant of the item kernel on the
+// batch's own items (targets of the next round, every trial from the same
+// saved instance state) and keeps the fastest.  The instance state and the
+// flip counter are restored afterwards, so the run continues exactly as it
+// would have without tuning (the variants compute identical results).
+int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
+    if (s->mlp_ops && !s->mlp) return dabs_fail(DABS_E_INVALID, "MLP operations enabled but no network attached");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t xw = 8 * (size_t)s->inst_words, i8 = 8 * (size_t)s->total_inst, i4 = 4 * (size_t)s->total_inst;
+    void *sx = nullptr, *sb = nullptr, *se = nullptr, *sbe = nullptr, *sph = nullptr, *sc = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int status = DABS_OK;
+    if (hipMalloc(&sx, xw) != hipSuccess || hipMalloc(&sb, xw) != hipSuccess || hipMalloc(&se, i8) != hipSuccess ||
+        hipMalloc(&sbe, i8) != hipSuccess || hipMalloc(&sph, i4) != hipSuccess || hipMalloc(&sc, 8) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        status = dabs_fail(DABS_E_NOMEM, "autotune scratch allocation failed");
+    auto copy = [&](void *dst, const void *src, size_t bytes) {
+        if (status == DABS_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            status = dabs_fail(DABS_E_HIP, "autotune copy failed");
+    };
+    copy(sx, s->d.x, xw); copy(sb, s->d.best, xw); copy(se, s->d.e, i8); copy(sbe, s->d.best_e, i8);
+    copy(sph, s->d.ph, i4); copy(sc, s->d.ctr, 8);
+    if (status == DABS_OK && s->mlp)
+        for (int p = 0; p < s->nprob && status == DABS_OK; ++p) {
+            const ProbDesc &d = s->hdesc[p];
+            status = mlp_pool_logits(s->probs[p], s->mlp, s->d.pool_bits + d.pool_word0, d.g.npools, d.g.capacity,
+                                     s->mlp_cnt, s->mlp_feat, s->mlp_logits + d.pool_bit0, st);
+        }
+    if (status == DABS_OK) {
+        hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
+                           (int)s->total_inst);
+        if (hipGetLastError() != hipSuccess) status = dabs_fail(DABS_E_HIP, "target generation failed");
+    }
+    for (size_t c = 0; c < s->classes.size() && status == DABS_OK; ++c) {
+        double best = 1e300;
+        int pick = 0;
+        for (int v = 0; v < WALK_VARIANTS && status == DABS_OK; ++v) {
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && status == DABS_OK; ++rep) {   // the first launch loads the code object
+                copy(s->d.x, sx, xw); copy(s->d.ph, sph, i4);
+                ItemsArgs a;
+                a.b = s->d;
+                a.items = s->items + s->classes[c].begin;
+                a.nitems = s->classes[c].count;
+                a.ttt = 0;
+                if (status == DABS_OK &&
+                    (hipEventRecord(e0, st) != hipSuccess ||
+                     launch_walk_items(s->classes[c].wtype, s->classes[c].slots, v, a, st) != hipSuccess ||
+                     hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    status = dabs_fail(DABS_E_HIP, "autotune trial failed");
+            }
+            if (ms_out) ms_out[c * WALK_VARIANTS + v] = ms;
+            if (ms < best) { best = ms; pick = v; }
+        }
+        s->classes[c].variant = pick;
+        if (choice_out) choice_out[c] = pick;
+    }
+    copy(s->d.x, sx, xw); copy(s->d.best, sb, xw); copy(s->d.e, se, i8); copy(s->d.best_e, sbe, i8);
+    copy(s->d.ph, sph, i4); copy(s->d.ctr, sc, 8);
+    if (hipStreamSynchronize(st) != hipSuccess && status == DABS_OK) status = dabs_fail(DABS_E_HIP, "autotune sync");
+    void *ptrs[] = {sx, sb, se, sbe, sph, sc};
+    for (void *q : ptrs) (void)hipFree(q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s->graph_ready) {            // the captured round has the old kernels
+        (void)hipGraphExecDestroy(s->exec);
+        (void)hipGraphDestroy(s->graph);
+        s->graph_ready = false;
+    }
+    return status;
+}
+
+int dabs_batched_classes(const dabs_batched *s, int32_t *wtype_slots_count_variant, int32_t cap) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
+    const int nc = (int)s->classes.size();
+    for (int c = 0; c < nc && c < cap && wtype_slots_count_variant; ++c) {
+        wtype_slots_count_variant[4 * c + 0] = s->classes[c].wtype;
+        wtype_slots_count_variant[4 * c + 1] = s->classes[c].slots;
+        wtype_slots_count_variant[4 * c + 2] = s->classes[c].count;
+        wtype_slots_count_variant[4 * c + 3] = s->classes[c].variant;
+    }
+    return nc;
+}
+
 int dabs_batched_set_mlp(dabs_batched *s, const dabs_mlp *m) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
     if (m && !s->mlp_logits) {
@@ -676,6 +763,11 @@ int dabs_solver_create(const dabs_problem *p, const dabs_ga_params *g, int32_t i
 int dabs_solver_set_mlp(dabs_solver *s, const dabs_mlp *m) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
     return dabs_batched_set_mlp(s->b, m);
+}
+
+int dabs_solver_autotune(dabs_solver *s, double *ms_out, int32_t *choice_out, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_autotune(s->b, ms_out, choice_out, stream);
 }
 
 int dabs_solver_destroy(dabs_solver *s) {

@@ -91,7 +91,10 @@ struct ItemsArgs {
     int32_t nitems;
     int32_t ttt;                   // record time to target
 };
-hipError_t launch_walk_items(int wtype, int slots, const ItemsArgs &a, hipStream_t stream);
+// Compiled variants of the item kernel per (weight type, slot count): 0 caps a
+// wave at 128 VGPRs (4 waves per SIMD), 1 leaves the register file uncapped.
+constexpr int WALK_VARIANTS = 2;
+hipError_t launch_walk_items(int wtype, int slots, int variant, const ItemsArgs &a, hipStream_t stream);
 // Largest n the walker kernels support for a weight type.
 int max_n(int wtype);
 

@@ -56,8 +56,10 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 // from an atomic counter inside a loop: with a lane-0 epilogue in the same
 // loop, the compiler may split it into nested loops so that lanes 1..63
 // re-enter the pop without lane 0 (and read item 0 again, forever).
-template <typename WT, int SLOTS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_items(ItemsArgs a) {
+// WPE: the minimum waves per SIMD the register allocation must allow (4 caps
+// a wave at 128 VGPRs; 1 leaves the whole register file to the allocator).
+template <typename WT, int SLOTS, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_walk_items(ItemsArgs a) {
     typedef typename Walker<WT, SLOTS>::vecE vecE;
     vecE h, s2, ex, key;
     const int lane = lane_id();
@@ -89,9 +91,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 template <typename WT, int SLOTS>
-static hipError_t go_items(const ItemsArgs &a, hipStream_t st) {
+static hipError_t go_items(int variant, const ItemsArgs &a, hipStream_t st) {
     if (a.nitems < 1) return hipSuccess;
-    hipLaunchKernelGGL((k_walk_items<WT, SLOTS>), dim3(a.nitems), dim3(WAVE), 0, st, a);
+    if (variant == 0)
+        hipLaunchKernelGGL((k_walk_items<WT, SLOTS, 4>), dim3(a.nitems), dim3(WAVE), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_walk_items<WT, SLOTS, 1>), dim3(a.nitems), dim3(WAVE), 0, st, a);
     return hipGetLastError();
 }
 
@@ -103,21 +108,22 @@ int walk_slots(int wtype, int n) {
     return p2;
 }
 
-hipError_t launch_walk_items(int wtype, int slots, const ItemsArgs &a, hipStream_t st) {
+hipError_t launch_walk_items(int wtype, int slots, int variant, const ItemsArgs &a, hipStream_t st) {
+    if (variant < 0 || variant >= WALK_VARIANTS) return hipErrorInvalidValue;
     if (wtype == DABS_W_I16) {
         switch (slots) {
-        case 1: return go_items<int16_t, 1>(a, st);
-        case 2: return go_items<int16_t, 2>(a, st);
-        case 4: return go_items<int16_t, 4>(a, st);
-        case 8: return go_items<int16_t, 8>(a, st);
+        case 1: return go_items<int16_t, 1>(variant, a, st);
+        case 2: return go_items<int16_t, 2>(variant, a, st);
+        case 4: return go_items<int16_t, 4>(variant, a, st);
+        case 8: return go_items<int16_t, 8>(variant, a, st);
         default: return hipErrorInvalidValue;
         }
     }
     switch (slots) {
-    case 1: return go_items<int32_t, 1>(a, st);
-    case 2: return go_items<int32_t, 2>(a, st);
-    case 4: return go_items<int32_t, 4>(a, st);
-    case 8: return go_items<int32_t, 8>(a, st);
+    case 1: return go_items<int32_t, 1>(variant, a, st);
+    case 2: return go_items<int32_t, 2>(variant, a, st);
+    case 4: return go_items<int32_t, 4>(variant, a, st);
+    case 8: return go_items<int32_t, 8>(variant, a, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,109 @@
+"""Parity at the full sizes of the workloads, on sampled outputs the oracle
+computes one at a time: after the first generational round every instance
+has run exactly one batch search from X = 0 towards a target drawn from the
+initial pools, so the oracle reproduces a sampled instance alone
+(first_target + batch_search) and its X, E and phase counter must equal the
+device's bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_03069_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2207_03069_amd as dabs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+CAP = 100000
+
+
+def og_params(g):
+    return oracle.ga_params(T=g.T, Bn=g.Bn, tau=g.tau, seed=g.seed, capacity=g.capacity, npools=g.npools,
+                            crossover_kind=g.crossover_kind, p_mutation=g.p_mutation, greedy_cap=g.greedy_cap)
+
+
+def check_sampled(W, g, x, e, ph, sample):
+    n = W.shape[0]
+    og = og_params(g)
+    for i in sample:
+        tgt, algo, _ = oracle.first_target(n, og, int(i))
+        r = oracle.batch_search(W, algo, np.zeros(n, np.uint8), tgt, T=g.T, Bn=g.Bn, tau=g.tau, seed=g.seed,
+                                inst=int(i), ph=0, greedy_cap=g.greedy_cap)
+        assert np.array_equal(x[i], r["x"]), i
+        assert e[i] == r["e"] and ph[i] == r["ph"], i
+
+
+def run_round1(W, g, instances):
+    n = W.shape[0]
+    p = dabs.dabs_problem_create(torch.from_numpy(W).to(DEV))
+    s = dabs.dabs_solver_create(p, g, instances)
+    dabs.dabs_solver_run(s, 1)
+    nw = (n + 63) // 64
+    x = torch.zeros((instances, nw), dtype=torch.int64, device=DEV)
+    e = torch.zeros(instances, dtype=torch.int64, device=DEV)
+    ph = torch.zeros(instances, dtype=torch.int32, device=DEV)
+    dabs.dabs_solver_state(s, x, e, ph)
+    torch.cuda.synchronize()
+    return (inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), e.cpu().numpy(),
+            ph.cpu().numpy().view(np.uint32))
+
+
+def sample(instances, seed, k=4):
+    rng = np.random.default_rng(seed)
+    return sorted({0, 1, instances // 2 + 3, instances - 1, *rng.integers(0, instances, k).tolist()})
+
+
+def test_maxcut800_4096_instances():
+    W, _, _ = inputs.maxcut_instance(800, 0.06, seed=0)
+    g = dabs.ga_params(T=80, Bn=8000, tau=8, seed=0, capacity=100, npools=8, greedy_cap=CAP)
+    x, e, ph = run_round1(W, g, 4096)
+    check_sampled(W, g, x, e, ph, sample(4096, 1))
+
+
+def test_tsp32_8192_instances():
+    """32 cities, one-hot encoding n = 1024, dense int32 W, A = 2 max d;
+    two-point crossover and 1 % mutation, s = 0.1, b = 1."""
+    W, D, A = inputs.tsp_instance(32, seed=0)
+    assert W.shape == (1024, 1024) and W.dtype == np.int32
+    g = dabs.ga_params(T=102, Bn=1024, tau=8, seed=0, capacity=100, npools=8, crossover_kind=1,
+                       p_mutation=oracle.P_ONE_PERCENT, greedy_cap=CAP)
+    x, e, ph = run_round1(W, g, 8192)
+    check_sampled(W, g, x, e, ph, sample(8192, 2))
+
+
+def test_dense2048_1024_instances():
+    W = inputs.dense_qubo(2048, -1000, 1000, 0)
+    g = dabs.ga_params(T=205, Bn=2048, tau=8, seed=0, capacity=100, npools=8, greedy_cap=CAP)
+    x, e, ph = run_round1(W, g, 1024)
+    check_sampled(W, g, x, e, ph, sample(1024, 3, 2))
+
+
+def test_batched_256_problems_graph_round():
+    """256 dense int16 problems, n log-uniform in [256, 4096), in one
+    graph-replayed round; sampled problems and instances."""
+    Ws = inputs.batched_problems(256, seed=0)
+    probs = [dabs.dabs_problem_create(torch.from_numpy(W).to(DEV)) for W in Ws]
+    params = [dabs.ga_params(T=max(1, round(0.1 * W.shape[0])), Bn=W.shape[0], tau=8, seed=1 + p, capacity=16,
+                             npools=2, greedy_cap=CAP) for p, W in enumerate(Ws)]
+    inst = 32
+    b = dabs.dabs_batched_create(probs, params, [inst] * 256)
+    dabs.dabs_batched_run(b, 1, None, use_graph=True)
+    rng = np.random.default_rng(4)
+    sizes = np.array([W.shape[0] for W in Ws])
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *rng.integers(0, 256, 4).tolist()})
+    for q in picks:
+        W = Ws[q]
+        n = W.shape[0]
+        nw = (n + 63) // 64
+        x = torch.zeros((inst, nw), dtype=torch.int64, device=DEV)
+        e = torch.zeros(inst, dtype=torch.int64, device=DEV)
+        ph = torch.zeros(inst, dtype=torch.int32, device=DEV)
+        dabs.dabs_batched_state(b, q, x, e, ph)
+        torch.cuda.synchronize()
+        check_sampled(W, params[q], inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), e.cpu().numpy(),
+                      ph.cpu().numpy().view(np.uint32), [0, 17, inst - 1])

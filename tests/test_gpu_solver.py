@@ -131,11 +131,17 @@ def test_solver_errors():
         dabs.dabs_solver_create(p, dabs.ga_params(T=2, Bn=10), 0)
 
 
-def batched_run(problems, params, instances, rounds, use_graph, target=None):
+def batched_run(problems, params, instances, rounds, use_graph, target=None, autotune=False):
     probs = [dabs.dabs_problem_create(torch.from_numpy(W).to(DEV)) for W in problems]
     b = dabs.dabs_batched_create(probs, params, instances)
-    tgt = None if target is None else torch.tensor(target, dtype=torch.int64, device=DEV)
-    dabs.dabs_batched_run(b, rounds, tgt, use_graph=use_graph)
+    if autotune:
+        dabs.dabs_batched_run(b, 1, None, use_graph=use_graph)     # tune on a round with real pools
+        ms, choice = dabs.dabs_batched_autotune(b)
+        assert len(ms) == len(dabs.dabs_batched_classes(b)) and all(v in (0, 1) for v in choice)
+        assert all(t > 0 for row in ms for t in row)
+        dabs.dabs_batched_run(b, rounds - 1, None, use_graph=use_graph)
+    else:
+        dabs.dabs_batched_run(b, rounds, tgt_or_none(target), use_graph=use_graph)
     out = []
     for q, W in enumerate(problems):
         n = W.shape[0]
@@ -155,8 +161,12 @@ def batched_run(problems, params, instances, rounds, use_graph, target=None):
     return out, prog.cpu().numpy()
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batched_parity_uneven_sizes(use_graph):
+def tgt_or_none(target):
+    return None if target is None else torch.tensor(target, dtype=torch.int64, device=DEV)
+
+
+@pytest.mark.parametrize("use_graph,autotune", [(False, False), (True, False), (True, True)])
+def test_batched_parity_uneven_sizes(use_graph, autotune):
     """Problems of uneven n and both weight types in one batch evolve exactly
     as the oracle runs each of them alone (graph replay included)."""
     sizes = [(40, np.int16), (300, np.int32), (700, np.int16), (130, np.int16), (1100, np.int16)]
@@ -166,7 +176,7 @@ def test_batched_parity_uneven_sizes(use_graph):
     instances = [6, 5, 4, 7, 3]
     rounds = 2
     got, prog = batched_run(problems, [dabs.ga_params(greedy_cap=CAP, **kw) for kw in kws], instances, rounds,
-                            use_graph)
+                            use_graph, autotune=autotune)
     for k, W in enumerate(problems):
         ref = oracle.solve(W, oracle.ga_params(greedy_cap=CAP, **kws[k]), instances[k], rounds)
         bits, pe, x, ph = got[k]
