@@ -25,6 +25,11 @@ namespace dabs {
 constexpr int WAVE = 64;
 constexpr int H_PAD = (1 << 23) - 1;     // local field of padding elements
 constexpr int KEY_BIG = 0x7fffffff;
+// Key of an element outside a rule's domain in masked minima.  Above every
+// real key (padding included: H_PAD << 6 < 2^29) but below INT_MAX, so that
+// min(m, in ? k : KEY_OUT) stays a select followed by a 3-input minimum (with
+// INT_MAX the compiler rewrites it as in ? min(m, k) : m, one more VALU op).
+constexpr int KEY_OUT = 0x7ffffff0;
 constexpr int TAU_MAX = 16;
 constexpr int64_t E_INF = INT64_MAX;
 
@@ -58,6 +63,31 @@ __device__ __forceinline__ R4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 __device__ __forceinline__ uint32_t scale32(uint32_t u, uint32_t m) {
     return (uint32_t)(((uint64_t)u * (uint64_t)m) >> 32);
 }
+
+// floor(t 2^32 / T) and its remainder for t = 0, 1, 2, ... (T >= 1): with
+// 2^32 = Q T + R the quotient and remainder step by (Q, R) and one carry, so
+// a phase divides once instead of once per iteration.
+struct FracStep {
+    uint64_t q, Q;      // floor(t 2^32 / T), floor(2^32 / T)
+    uint32_t r, R, T;   // (t 2^32) mod T, 2^32 mod T
+    __device__ __forceinline__ void init(uint32_t T_) {
+        T = T_;
+        Q = (1ull << 32) / T_;
+        R = (uint32_t)((1ull << 32) % T_);
+        q = 0;
+        r = 0;
+    }
+    __device__ __forceinline__ void next() {
+        q += Q;
+        r += R;
+        if (r >= T) {
+            r -= T;
+            q += 1;
+        }
+    }
+    // floor((T - t) 2^32 / T) = 2^32 - ceil(t 2^32 / T)
+    __device__ __forceinline__ uint64_t rest() const { return (1ull << 32) - q - (r != 0 ? 1 : 0); }
+};
 
 // 32.32 fixed-point cube, floor-chained.
 __device__ __forceinline__ uint64_t cube_frac(uint64_t f) { return (((f * f) >> 32) * f) >> 32; }
@@ -107,6 +137,31 @@ __device__ __forceinline__ void wave_min2(int a, int b, int &ra, int &rb) {
     rb = min(min(readlane(b, 0), readlane(b, 16)), min(readlane(b, 32), readlane(b, 48)));
 }
 __device__ __forceinline__ int wave_max(int v) { return wave_ext<true>(v); }
+
+// Wave min of a and b and wave max of c, reduced together (interleaved DPP
+// chains; c ends in a max).
+__device__ __forceinline__ void wave_minmin_max(int a, int b, int c, int &ra, int &rb, int &rc) {
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0xB1, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0xB1, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0xB1, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x4E, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0x4E, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0x4E, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x141, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0x141, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0x141, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x140, 0xF, 0xF, true));
+    b = min(b, __builtin_amdgcn_mov_dpp(b, 0x140, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0x140, 0xF, 0xF, true));
+    ra = min(min(readlane(a, 0), readlane(a, 16)), min(readlane(a, 32), readlane(a, 48)));
+    rb = min(min(readlane(b, 0), readlane(b, 16)), min(readlane(b, 32), readlane(b, 48)));
+    rc = max(max(readlane(c, 0), readlane(c, 16)), max(readlane(c, 32), readlane(c, 48)));
+}
+
+// value of the neighbouring lane (l xor 1)
+__device__ __forceinline__ uint32_t swap_pair(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
     int lo = __shfl_xor((int)(uint32_t)v, m, WAVE), hi = __shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);

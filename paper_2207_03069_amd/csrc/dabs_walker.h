@@ -224,13 +224,13 @@ struct Walker {
         for (int j = 0; j < EPL; j += 2) m = min(m, min(K(j), K(j + 1)));
         return m;
     }
-    // least key among elements with ex < thr
+    // least key among elements with ex < thr (KEY_OUT when there is none)
     __device__ __forceinline__ int lane_min_dom(int thr) const {
-        int m = KEY_BIG;
+        int m = KEY_OUT;
 #pragma unroll
         for (int j = 0; j < EPL; j += 2) {
-            const int a = ex[j] < thr ? K(j) : KEY_BIG;
-            const int b = ex[j + 1] < thr ? K(j + 1) : KEY_BIG;
+            const int a = ex[j] < thr ? K(j) : KEY_OUT;
+            const int b = ex[j + 1] < thr ? K(j + 1) : KEY_OUT;
             m = min(m, min(a, b));
         }
         return m;
@@ -293,6 +293,30 @@ struct Walker {
         wave_min2(kminU >> LOGV, kminM >> LOGV, mU, mM);
         step1();
     }
+    // MaxMin's reductions of the domain ex < thr, made in the pass that
+    // recomputes the keys after a flip: least key kminM / mM (as
+    // refresh_dom) and greatest key mX (its wave maximum).
+    int mX;
+    __device__ __forceinline__ void dom_minmax(int thr) {
+        int ku = KEY_BIG, km = KEY_OUT, kx = -KEY_OUT;
+#pragma unroll
+        for (int j = 0; j < EPL; j += 2) {
+            const int k0 = K(j), k1 = K(j + 1);
+            const bool i0 = ex[j] < thr, i1 = ex[j + 1] < thr;
+            ku = min(ku, min(k0, k1));
+            km = min(km, min(i0 ? k0 : KEY_OUT, i1 ? k1 : KEY_OUT));
+            kx = max(kx, max(i0 ? k0 : -KEY_OUT, i1 ? k1 : -KEY_OUT));
+        }
+        kminU = ku;
+        kminM = km;
+        wave_minmin_max(ku >> LOGV, km >> LOGV, kx, mU, mM, mX);
+    }
+    __device__ __forceinline__ void refresh_minmax(int thr) {
+        compute_keys();
+        dom_minmax(thr);
+        step1();
+    }
+
     // argmin of the domain reduced by refresh_dom, or the plain argmin when
     // the domain is empty
     __device__ __forceinline__ Sel dom_sel() const {
@@ -416,12 +440,15 @@ struct Walker {
     // CyclicMin (Section III-A.4): argmin over a sliding cyclic window.
     __device__ __forceinline__ int phase_cyclicmin(int T, int tau) {
         int pos = 0;
+        FracStep fs;
+        fs.init((uint32_t)T);
         for (int t = 1; t <= T; ++t) {
+            fs.next();                      // fs.q = floor(t 2^32 / T)
             int w;
             if (t >= T) {
                 w = n;
             } else {
-                const uint64_t hh = ((uint64_t)t << 32) / (uint64_t)T;
+                const uint64_t hh = fs.q;
                 const int c = n < 32 ? n : 32;
                 const int64_t ww = (int64_t)(((uint64_t)n * cube_frac(hh)) >> 32);
                 w = ww < c ? c : (ww > n ? n : (int)ww);
@@ -525,37 +552,58 @@ struct Walker {
         return EX_ALWAYS;
     }
 
-    // MaxMin (Section III-A.3).
+    // MaxMin (Section III-A.3).  The domain reductions of iteration t+1 (its
+    // least and greatest key) are made by the refresh after the flip of
+    // iteration t; the tabu mark of iteration t precedes that flip.
     __device__ __forceinline__ int phase_maxmin(int T, int tau, uint32_t ph) {
+        dom_minmax(1);                      // iteration 1: nothing is tabu
+        FracStep fs;
+        fs.init((uint32_t)T);
         for (int t = 1; t <= T; ++t) {
-            int km, mm;
-            const int thr = domain(t, km, mm);
-            const int mind = mm >> SB;
-            int kx = -KEY_BIG;
+            fs.next();
+            int thr = t;
+            if (empty_dom(mM)) {            // every bit tabu: tabu ignored (R11)
+                thr = EX_ALWAYS;
+                mM = mU;
+                int kx = -KEY_OUT;
 #pragma unroll
-            for (int j = 0; j < EPL; ++j) kx = max(kx, ex[j] < thr ? K(j) : -KEY_BIG);
-            const int maxd = wave_max(kx) >> KB;
+                for (int j = 0; j < EPL; ++j) kx = max(kx, ex[j] < thr ? K(j) : -KEY_OUT);
+                mX = wave_max(kx);
+            }
+            const int mind = mM >> SB;
+            const int maxd = mX >> KB;
             const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
-            const uint64_t g = ((uint64_t)(T - t) << 32) / (uint64_t)T;
+            const uint64_t g = fs.rest();   // floor(2^32 (T - t) / T)
             const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cube_frac(g)) >> 32;
             const int d = mind + (int)(((uint64_t)r.w[0] * (span + 1)) >> 32);
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
             const Sel s = pick_rth(dk, thr, r.w[1]);
-            flip(s);
             mark_tabu(s, t, tau);
+            flip_core(s);
+            refresh_minmax(t + 1);
         }
         ex_reset();
         return T;
     }
 
-    // PositiveMin (Section III-A.6).
+    // PositiveMin (Section III-A.6).  Its domain's least key only decides
+    // whether the domain is empty; with n > tau at most tau bits are tabu, so
+    // it never is and that reduction is skipped.
     __device__ __forceinline__ int phase_positivemin(int T, int tau, uint32_t ph) {
+        const bool may_empty = n <= tau;
         for (int t = 1; t <= T; ++t) {
-            int km, mm;
-            const int thr = domain(t, km, mm);
-            int kp = KEY_BIG;
+            int thr = t;
+            if (may_empty) {
+                int km, mm;
+                thr = domain(t, km, mm);
+            }
+            int kp = KEY_OUT;
 #pragma unroll
-            for (int j = 0; j < EPL; ++j) kp = min(kp, (ex[j] < thr && K(j) >= (1 << KB)) ? K(j) : KEY_BIG);
+            for (int j = 0; j < EPL; j += 2) {
+                const int a = (ex[j] < thr && K(j) >= (1 << KB)) ? K(j) : KEY_OUT;
+                const int b = (ex[j + 1] < thr && K(j + 1) >= (1 << KB)) ? K(j + 1) : KEY_OUT;
+                kp = min(kp, min(a, b));
+            }
             const int pd = wave_min(kp >> LOGV) >> SB;
             const int d = pd >= H_PAD ? H_PAD - 1 : pd;
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
@@ -570,31 +618,57 @@ struct Walker {
 
     // RandomMin (Section III-A.5): candidates by random byte < q(t).
     __device__ __forceinline__ int phase_randommin(int T, int tau, uint32_t ph) {
+        FracStep fs;
+        fs.init((uint32_t)T);
         for (int t = 1; t <= T; ++t) {
+            fs.next();
             int q;
             if (t >= T) {
                 q = 256;
             } else {
-                const uint64_t hh = ((uint64_t)t << 32) / (uint64_t)T;
+                const uint64_t hh = fs.q;
                 const int qq = (int)(cube_frac(hh) >> 24);
                 const int qmin = (8192 + n - 1) / n;
                 q = qq < qmin ? qmin : (qq > 256 ? 256 : qq);
             }
-            int kr = KEY_BIG;
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                const int k0 = s * SPAN + lane * V;
-                const R4 r = philox((uint32_t)t, inst, ph, ((uint32_t)TAG_RANDMIN << 24) | (uint32_t)(k0 >> 4), seed);
-                // this lane's V bytes start at byte (k0 mod 16) of the draw
-                const int w0 = (k0 & 15) >> 2;
-                const uint32_t wa = w0 == 0 ? r.w[0] : (w0 == 1 ? r.w[1] : (w0 == 2 ? r.w[2] : r.w[3]));
-                const uint32_t wb = w0 == 0 ? r.w[1] : (w0 == 1 ? r.w[2] : r.w[3]);
+            int kr = KEY_OUT;
+            // lane's random words for slot s: wa (bytes of elements 0..3), wb (4..7)
+            auto cand = [&](int s, uint32_t wa, uint32_t wb) {
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     const int j = s * V + e;
                     const uint32_t word = e < 4 ? wa : wb;
                     const int byte = (int)((word >> (8 * (e & 3))) & 0xFFu);
-                    kr = min(kr, (byte < q && ex[j] < t) ? K(j) : KEY_BIG);
+                    kr = min(kr, (byte < q && ex[j] < t) ? K(j) : KEY_OUT);
+                }
+            };
+            const uint32_t tag = (uint32_t)TAG_RANDMIN << 24;
+            if constexpr (V == 8 && SLOTS % 2 == 0) {
+                // Lanes 2m and 2m+1 share the draw of bits 16m .. 16m+15 of a
+                // slot (bytes 0..7 and 8..15).  Even lanes draw for even slots,
+                // odd lanes for odd slots, and each pair swaps the halves.
+                const bool odd = lane & 1;
+#pragma unroll
+                for (int u = 0; u < SLOTS; u += 2) {
+                    const int s_own = u + (odd ? 1 : 0);
+                    const R4 r = philox((uint32_t)t, inst, ph, tag | (uint32_t)((s_own * SPAN + lane * V) >> 4), seed);
+                    const uint32_t ra = swap_pair(odd ? r.w[0] : r.w[2]);
+                    const uint32_t rb = swap_pair(odd ? r.w[1] : r.w[3]);
+                    // slot u: even lane own words 0, 1; odd lane the even neighbour's 2, 3
+                    cand(u, odd ? ra : r.w[0], odd ? rb : r.w[1]);
+                    // slot u+1: even lane the odd neighbour's 0, 1; odd lane own 2, 3
+                    cand(u + 1, odd ? r.w[2] : ra, odd ? r.w[3] : rb);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    const int k0 = s * SPAN + lane * V;
+                    const R4 r = philox((uint32_t)t, inst, ph, tag | (uint32_t)(k0 >> 4), seed);
+                    // this lane's V bytes start at byte (k0 mod 16) of the draw
+                    const int w0 = (k0 & 15) >> 2;
+                    const uint32_t wa = w0 == 0 ? r.w[0] : (w0 == 1 ? r.w[1] : (w0 == 2 ? r.w[2] : r.w[3]));
+                    const uint32_t wb = w0 == 0 ? r.w[1] : (w0 == 1 ? r.w[2] : r.w[3]);
+                    cand(s, wa, wb);
                 }
             }
             const int m = wave_min(kr >> LOGV);
