@@ -379,15 +379,18 @@ static int64_t phase_maxmin(state_t *st, int64_t T, int32_t tau, uint32_t ph)
                 if (st->delta[k] < mind) mind = st->delta[k];
                 if (st->delta[k] > maxd) maxd = st->delta[k];
             }
+        /* R18: iterations 2c+1 and 2c+2 use words (0, 1) and (2, 3) of draw c */
         uint32_t r[4];
-        draw4(st->seed, (uint32_t)t, st->inst, ph, (uint32_t)TAG_MAXMIN << 24, r);
-        int64_t d = maxmin_threshold(t, T, mind, maxd, r[0]);
+        const int64_t half = (t - 1) % 2;
+        draw4(st->seed, (uint32_t)((t - 1) / 2), st->inst, ph, (uint32_t)TAG_MAXMIN << 24, r);
+        const uint32_t u = r[2 * half], v = r[2 * half + 1];
+        int64_t d = maxmin_threshold(t, T, mind, maxd, u);
         int64_t c = 0;
         for (int32_t k = 0; k < n; k++) {
             cand[k] = dom[k] && st->delta[k] <= d;
             c += cand[k];
         }
-        int32_t j = nth_marked(cand, n, (int64_t)scale_u32(r[1], (uint32_t)c));
+        int32_t j = nth_marked(cand, n, (int64_t)scale_u32(v, (uint32_t)c));
         flip(st, j);
         tb.last[j] = t;
     }
@@ -463,9 +466,10 @@ static int64_t phase_positivemin(state_t *st, int64_t T, int32_t tau, uint32_t p
             cand[k] = dom[k] && (posmin == INT64_MAX || st->delta[k] <= posmin);
             c += cand[k];
         }
+        /* R18: iterations 4c+1 .. 4c+4 use words 0 .. 3 of draw c */
         uint32_t r[4];
-        draw4(st->seed, (uint32_t)t, st->inst, ph, (uint32_t)TAG_POSMIN << 24, r);
-        int32_t j = nth_marked(cand, n, (int64_t)scale_u32(r[0], (uint32_t)c));
+        draw4(st->seed, (uint32_t)((t - 1) / 4), st->inst, ph, (uint32_t)TAG_POSMIN << 24, r);
+        int32_t j = nth_marked(cand, n, (int64_t)scale_u32(r[(t - 1) % 4], (uint32_t)c));
         flip(st, j);
         tb.last[j] = t;
     }

@@ -559,6 +559,7 @@ struct Walker {
         dom_minmax(1);                      // iteration 1: nothing is tabu
         FracStep fs;
         fs.init((uint32_t)T);
+        R4 r = {{0u, 0u, 0u, 0u}};
         for (int t = 1; t <= T; ++t) {
             fs.next();
             int thr = t;
@@ -572,12 +573,14 @@ struct Walker {
             }
             const int mind = mM >> SB;
             const int maxd = mX >> KB;
-            const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
+            // iterations 2c+1 and 2c+2 use words (0, 1) and (2, 3) of draw c (R18)
+            if (!((t - 1) & 1)) r = philox((uint32_t)((t - 1) >> 1), inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
+            const uint32_t u = ((t - 1) & 1) ? r.w[2] : r.w[0], v = ((t - 1) & 1) ? r.w[3] : r.w[1];
             const uint64_t g = fs.rest();   // floor(2^32 (T - t) / T)
             const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cube_frac(g)) >> 32;
-            const int d = mind + (int)(((uint64_t)r.w[0] * (span + 1)) >> 32);
+            const int d = mind + (int)(((uint64_t)u * (span + 1)) >> 32);
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
-            const Sel s = pick_rth(dk, thr, r.w[1]);
+            const Sel s = pick_rth(dk, thr, v);
             mark_tabu(s, t, tau);
             flip_core(s);
             refresh_minmax(t + 1);
@@ -591,6 +594,7 @@ struct Walker {
     // it never is and that reduction is skipped.
     __device__ __forceinline__ int phase_positivemin(int T, int tau, uint32_t ph) {
         const bool may_empty = n <= tau;
+        R4 r = {{0u, 0u, 0u, 0u}};
         for (int t = 1; t <= T; ++t) {
             int thr = t;
             if (may_empty) {
@@ -607,8 +611,11 @@ struct Walker {
             const int pd = wave_min(kp >> LOGV) >> SB;
             const int d = pd >= H_PAD ? H_PAD - 1 : pd;
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
-            const R4 r = philox((uint32_t)t, inst, ph, (uint32_t)TAG_POSMIN << 24, seed);
-            const Sel s = pick_rth(dk, thr, r.w[0]);
+            // iterations 4c+1 .. 4c+4 use words 0 .. 3 of draw c (R18)
+            if (!((t - 1) & 3)) r = philox((uint32_t)((t - 1) >> 2), inst, ph, (uint32_t)TAG_POSMIN << 24, seed);
+            const int q4 = (t - 1) & 3;
+            const uint32_t u = q4 == 0 ? r.w[0] : (q4 == 1 ? r.w[1] : (q4 == 2 ? r.w[2] : r.w[3]));
+            const Sel s = pick_rth(dk, thr, u);
             flip(s);
             mark_tabu(s, t, tau);
         }
