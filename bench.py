@@ -129,22 +129,28 @@ def _first_hits(solver_run, progress, rounds_cap, nprob, dev):
     return [float(v) / 1e8 if v >= 0 else None for v in h], r
 
 
-def learned_vs_plain(dev, n=2048, instances=512, ref_rounds=32, cap=96):
+def learned_vs_plain(dev, n=2000, instances=256, npools=4, capacity=50, ref_rounds=100, cap=300,
+                     collect_rounds=500, seeds=(1, 2, 3, 4, 5)):
     """Time to target of the plain DABS loop and of the loop with the learned
-    operations on a dense n = 2048 int16 QUBO (U[-1000, 1000], seed 0), after
-    training the network on pool solutions of a plain run on another problem
-    of the same family (seed 1).  Target: the best energy of a plain reference
-    run with another seed after ref_rounds rounds."""
+    operations on a K2000-like max-cut (complete graph, n = 2000, +-1 weights,
+    seed 0), after training the network on 10^5 pool solutions of a plain run
+    on another graph of the family (seed 1).  Target: the best energy of a
+    plain reference run with another seed after ref_rounds rounds."""
     import torch
     import paper_2207_03069_amd as dabs
     from paper_2207_03069_amd import train
+
+    def problem(seed):
+        W, _, _ = inputs.maxcut_instance(n, 1.0, seed=seed)
+        return dabs.dabs_problem_create(torch.from_numpy(W).to(dev))
     T, Bn = round(S_FACTOR * n), n                      # s = 0.1, b = 1
 
     def params(seed, ops=tuple(range(8))):
-        return dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=seed, capacity=CAPACITY, npools=NPOOLS, ops=ops)
+        return dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=seed, capacity=capacity, npools=npools, ops=ops)
     t0 = time.perf_counter()
-    ptr = dabs.dabs_problem_create(torch.from_numpy(inputs.dense_qubo(n, -1000, 1000, 1)).to(dev))
-    feats, labels, _ = train.collect(ptr, params(101), instances=instances, rounds=125, every=1)  # 10^5 pooled vectors
+    ptr = problem(1)
+    feats, labels, _ = train.collect(ptr, params(101), instances=instances, rounds=collect_rounds, every=1,
+                                     symmetric=True)          # max-cut: E(x) = E(not x)
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
     t1 = time.perf_counter()
@@ -152,8 +158,26 @@ def learned_vs_plain(dev, n=2048, instances=512, ref_rounds=32, cap=96):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     nsamp = int(feats.shape[0])
-    del feats, labels, ptr
-    prob = dabs.dabs_problem_create(torch.from_numpy(inputs.dense_qubo(n, -1000, 1000, 0)).to(dev))
+    # matrix-core roofline of the network kernels over the whole training set:
+    # algorithmic 2 (8*64 + 64*64 + 64) = 9344 FLOP per sample forward, three
+    # times that for forward + backward (the gradient kernel recomputes the
+    # forward pass)
+    logits = torch.empty(nsamp, dtype=torch.float32, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    dabs.dabs_mlp_forward(net, nsamp, feats, logits)               # warm
+    ev[0].record()
+    dabs.dabs_mlp_forward(net, nsamp, feats, logits)
+    ev[1].record()
+    dabs.dabs_mlp_grad(net, nsamp, feats, labels)
+    ev[2].record()
+    torch.cuda.synchronize()
+    ms_f, ms_g = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    fl_f, fl_g = 9344.0 * nsamp, 3 * 9344.0 * nsamp
+    mlp_roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": 2500.0, "samples": nsamp,
+                "forward": {"ms": ms_f, "achieved": fl_f / ms_f / 1e9, "frac": fl_f / ms_f / 1e9 / 2500.0},
+                "gradient": {"ms": ms_g, "achieved": fl_g / ms_g / 1e9, "frac": fl_g / ms_g / 1e9 / 2500.0}}
+    del feats, labels, ptr, logits
+    prob = problem(0)
     ref = dabs.dabs_solver_create(prob, params(999), instances)
     dabs.dabs_solver_autotune(ref)
     dabs.dabs_solver_run(ref, ref_rounds)
@@ -166,7 +190,7 @@ def learned_vs_plain(dev, n=2048, instances=512, ref_rounds=32, cap=96):
     res = {}
     for name, ops in (("plain", tuple(range(8))), ("learned", tuple(range(10)))):
         hits, rounds = [], []
-        for seed in (1, 2, 3, 4, 5):
+        for seed in seeds:
             s = dabs.dabs_solver_create(prob, params(seed, ops), instances)
             if name == "learned":
                 dabs.dabs_solver_set_mlp(s, net)
@@ -185,11 +209,13 @@ def learned_vs_plain(dev, n=2048, instances=512, ref_rounds=32, cap=96):
         res[name] = {"seconds_per_seed": hits, "rounds_per_seed": rounds,
                      "median_s": float(np.median([x if x is not None else np.inf for x in hits])),
                      "reached": len(ok), "runs": len(hits)}
-    return {"problem": "dense int16 QUBO n=%d U[-1000,1000] seed 0, %d instances, 8 pools x 100, s=0.1 b=1"
-                       % (n, instances),
+    return {"problem": "K2000-like max-cut: complete graph n=%d, +-1 weights, seed 0; %d instances, %d pools x %d, "
+                       "s=0.1 b=1" % (n, instances, npools, capacity),
             "target_e": target, "target_from": "plain run, seed 999, %d rounds" % ref_rounds, "round_cap": cap,
             "training": {"problem": "same family, seed 1", "pool_solutions": nsamp // n, "samples": nsamp,
+                         "labels": "bit differs from the nearer of the run's best vector and its complement",
                          "epochs": len(hist), "loss_per_epoch": hist, "collect_s": t_collect, "train_s": t_train},
+            "mlp_roofline": mlp_roof,
             "plain": res["plain"], "learned": res["learned"]}
 
 

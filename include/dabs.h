@@ -333,9 +333,12 @@ int dabs_mlp_params(const dabs_mlp *m, float *params_dev, void *stream);
  * the stream. */
 int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev, int32_t npools, int32_t capacity,
                            uint16_t *feat_dev, void *stream);
-/* labels_dev[e][k] = bit k of bits_dev[e] != bit k of ref_dev (u8, count x n). */
+/* labels_dev[e][k] = bit k of bits_dev[e] != bit k of ref_dev (u8, count x n).
+ * symmetric != 0: against ref or its complement, whichever is nearer in
+ * Hamming distance (ties: ref) -- for problems whose energy is invariant under
+ * complementing every bit, such as max-cut (Section II-A). */
 int dabs_mlp_labels(const dabs_problem *p, const uint64_t *bits_dev, int64_t count, const uint64_t *ref_dev,
-                    uint8_t *labels_dev, void *stream);
+                    int32_t symmetric, uint8_t *labels_dev, void *stream);
 /* logits_dev[count] float32 of the samples feat_dev[count][8]. */
 int dabs_mlp_forward(const dabs_mlp *m, int64_t count, const uint16_t *feat_dev, float *logits_dev, void *stream);
 /* Gradient of the mean loss over `count` samples into the network's gradient

@@ -114,6 +114,17 @@ def features(W, X, pool_bits, rank):
     return bf16(f)
 
 
+def labels(X, ref, symmetric=False):
+    """1 where bit k of X differs from the reference; with symmetric, from the
+    reference or its complement, whichever is nearer (ties: the reference)."""
+    X = np.asarray(X, dtype=np.uint8)
+    ref = np.asarray(ref, dtype=np.uint8)
+    d = X ^ ref
+    if symmetric and 2 * int(d.sum()) > X.shape[0]:
+        d = 1 - d
+    return d.astype(np.uint8)
+
+
 # ------------------------------------------------------------------ network
 def _r(x, rounding):
     return bf16(x.astype(np.float32)).astype(np.float64) if rounding else x

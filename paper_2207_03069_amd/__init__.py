@@ -85,7 +85,7 @@ _SIGS = {
     "dabs_mlp_destroy": ([_P], C.c_int),
     "dabs_mlp_params": ([_P, _P, _P], C.c_int),
     "dabs_mlp_pool_features": ([_P, _P, C.c_int32, C.c_int32, _P, _P], C.c_int),
-    "dabs_mlp_labels": ([_P, _P, C.c_int64, _P, _P, _P], C.c_int),
+    "dabs_mlp_labels": ([_P, _P, C.c_int64, _P, C.c_int32, _P, _P], C.c_int),
     "dabs_mlp_forward": ([_P, C.c_int64, _P, _P, _P], C.c_int),
     "dabs_mlp_grad": ([_P, C.c_int64, _P, _P, _P, _P, _P], C.c_int),
     "dabs_mlp_adam": ([_P, C.c_float, _P], C.c_int),
@@ -362,8 +362,9 @@ def dabs_mlp_pool_features(p: Problem, pool_bits, npools: int, capacity: int, fe
     _check(lib().dabs_mlp_pool_features(p.handle, _ptr(pool_bits), npools, capacity, _ptr(feat), _stream(stream)))
 
 
-def dabs_mlp_labels(p: Problem, bits, count: int, ref, labels, stream=None):
-    _check(lib().dabs_mlp_labels(p.handle, _ptr(bits), count, _ptr(ref), _ptr(labels), _stream(stream)))
+def dabs_mlp_labels(p: Problem, bits, count: int, ref, labels, symmetric: bool = False, stream=None):
+    _check(lib().dabs_mlp_labels(p.handle, _ptr(bits), count, _ptr(ref), int(symmetric), _ptr(labels),
+                                 _stream(stream)))
 
 
 def dabs_mlp_forward(m: Mlp, count: int, feat, logits, stream=None):

@@ -374,14 +374,33 @@ __global__ __launch_bounds__(256) void k_features(const WT *__restrict__ W, cons
     }
 }
 
-// label[e][k] = 1 when bit k of vector e differs from the reference vector.
-__global__ void k_labels(const uint64_t *__restrict__ bits, int64_t count, int n, int nw,
-                         const uint64_t *__restrict__ ref, uint8_t *__restrict__ label) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count * n) return;
-    const int64_t e = t / n;
-    const int k = (int)(t % n);
-    label[t] = (uint8_t)(((bits[e * nw + (k >> 6)] ^ ref[k >> 6]) >> (k & 63)) & 1);
+// label[e][k] = 1 when bit k of vector e differs from the reference vector;
+// with sym, from the reference or its complement, whichever is nearer in
+// Hamming distance (ties: the reference).  One workgroup per vector.
+__global__ __launch_bounds__(256) void k_labels(const uint64_t *__restrict__ bits, int n, int nw,
+                                                const uint64_t *__restrict__ ref, int sym,
+                                                uint8_t *__restrict__ label) {
+    const int64_t e = blockIdx.x;
+    const uint64_t *x = bits + e * nw;
+    bool flip = false;
+    if (sym) {
+        __shared__ int part[256];
+        int d = 0;
+        for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+            uint64_t v = x[w] ^ ref[w];
+            if (w == nw - 1 && (n & 63)) v &= (1ull << (n & 63)) - 1;
+            d += __builtin_popcountll(v);
+        }
+        part[threadIdx.x] = d;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+            __syncthreads();
+        }
+        flip = 2 * part[0] > n;
+    }
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        label[e * n + k] = (uint8_t)((((x[k >> 6] ^ ref[k >> 6]) >> (k & 63)) & 1) ^ (flip ? 1 : 0));
 }
 
 __global__ void k_apply_op(int op, int n, int nw, int count, const uint64_t *__restrict__ parent,
@@ -488,12 +507,12 @@ int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev,
 }
 
 int dabs_mlp_labels(const dabs_problem *p, const uint64_t *bits_dev, int64_t count, const uint64_t *ref_dev,
-                    uint8_t *labels_dev, void *stream) {
-    if (!p || !bits_dev || !ref_dev || !labels_dev || count < 0) return dabs_fail(DABS_E_INVALID, "bad argument");
-    const int64_t tot = count * p->n;
-    if (tot == 0) return DABS_OK;
-    hipLaunchKernelGGL(k_labels, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, (hipStream_t)stream, bits_dev,
-                       count, p->n, (p->n + 63) / 64, ref_dev, labels_dev);
+                    int32_t symmetric, uint8_t *labels_dev, void *stream) {
+    if (!p || !bits_dev || !ref_dev || !labels_dev || count < 0 || count > 0x7fffffff)
+        return dabs_fail(DABS_E_INVALID, "bad argument");
+    if (count == 0) return DABS_OK;
+    hipLaunchKernelGGL(k_labels, dim3((unsigned)count), dim3(256), 0, (hipStream_t)stream, bits_dev, p->n,
+                       (p->n + 63) / 64, ref_dev, symmetric ? 1 : 0, labels_dev);
     HIP_OK(hipGetLastError());
     return DABS_OK;
 }

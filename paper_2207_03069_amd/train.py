@@ -8,7 +8,9 @@ Data: a plain solver runs `rounds` generational rounds; every `every` rounds
 its pools are snapshotted on the device.  After the run, every snapshotted
 entry's bits are labelled against the best vector of the whole run
 (label 1 = the bit differs), so the network learns which bits of a pooled
-vector the search later ended up flipping.
+vector the search later ended up flipping.  For problems invariant under
+complementing every bit (max-cut) the label is taken against the best vector
+or its complement, whichever is nearer.
 """
 from __future__ import annotations
 
@@ -28,7 +30,7 @@ def init_params(seed: int) -> np.ndarray:
     return p.astype(np.float32)
 
 
-def collect(problem, params, instances: int, rounds: int, every: int):
+def collect(problem, params, instances: int, rounds: int, every: int, symmetric: bool = False):
     """Runs the plain solver and returns (features [S][8] bf16 as int16,
     labels [S] u8) on the device for all snapshotted pool entries."""
     import torch
@@ -54,7 +56,7 @@ def collect(problem, params, instances: int, rounds: int, every: int):
     for i, b in enumerate(snaps):
         sl = slice(i * P * m, (i + 1) * P * m)
         dabs_mlp_pool_features(problem, b, P, m, feats[sl])
-        dabs_mlp_labels(problem, b, P * m, best_bits, labels[sl])
+        dabs_mlp_labels(problem, b, P * m, best_bits, labels[sl], symmetric)
     return feats.reshape(-1, 8), labels.reshape(-1), best_e
 
 

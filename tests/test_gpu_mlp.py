@@ -56,17 +56,23 @@ def test_features_bit_exact(n, wt, P, m):
             assert np.array_equal(got[q, r], exp), (q, r)
 
 
-def test_labels_bit_exact():
-    n = 130
+@pytest.mark.parametrize("n", [130, 64, 1])
+def test_labels_bit_exact(n):
     W = inputs.dense_qubo(n, -5, 5, 1)
     p = dabs.dabs_problem_create(dev(W))
-    rng = np.random.default_rng(0)
-    X = rng.integers(0, 2, (9, n)).astype(np.uint8)
+    rng = np.random.default_rng(n)
     ref = rng.integers(0, 2, n).astype(np.uint8)
-    lab = torch.zeros((9, n), dtype=torch.uint8, device=DEV)
-    dabs.dabs_mlp_labels(p, packed(X), 9, packed(ref[None])[0], lab)
-    torch.cuda.synchronize()
-    assert np.array_equal(lab.cpu().numpy(), X ^ ref[None])
+    X = rng.integers(0, 2, (9, n)).astype(np.uint8)
+    X[0] = ref
+    X[1] = 1 - ref                                  # the complement
+    X[2, : n // 8] = 1 - ref[: n // 8]              # near the reference
+    X[2, n // 8:] = ref[n // 8:]
+    for sym in (False, True):
+        lab = torch.zeros((9, n), dtype=torch.uint8, device=DEV)
+        dabs.dabs_mlp_labels(p, packed(X), 9, packed(ref[None])[0], lab, sym)
+        torch.cuda.synchronize()
+        exp = np.stack([omlp.labels(x, ref, sym) for x in X])
+        assert np.array_equal(lab.cpu().numpy(), exp), sym
 
 
 @pytest.mark.parametrize("op", [dabs.DABS_OP_MLP_SEED, dabs.DABS_OP_MLP_MUTATE])
@@ -242,3 +248,28 @@ def test_learned_operations_need_a_network():
     s = dabs.dabs_solver_create(p, dabs.ga_params(T=2, Bn=40, ops=(dabs.DABS_OP_MLP_SEED,)), 4)
     with pytest.raises(dabs.DabsError):
         dabs.dabs_solver_run(s, 1)
+
+
+def test_training_on_plain_search_solutions_generalises():
+    """The network trained on pool solutions of plain runs on one max-cut
+    graph predicts the flips of pool solutions on another graph of the
+    family better than the untrained network (held-out loss)."""
+    from paper_2207_03069_amd import train
+    n = 256
+
+    def data(seed):
+        W, _, _ = inputs.maxcut_instance(n, 0.2, seed=seed)
+        p = dabs.dabs_problem_create(dev(W))
+        g = dabs.ga_params(T=26, Bn=n, tau=8, seed=seed, capacity=20, npools=2)
+        return train.collect(p, g, instances=64, rounds=40, every=2, symmetric=True)[:2]
+    f_tr, y_tr = data(1)
+    f_te, y_te = data(2)
+    untrained = dabs.dabs_mlp_create(train.init_params(0))
+    net, hist = train.fit(f_tr, y_tr, epochs=3, batch=1 << 14, lr=3e-3, seed=0)
+    loss = torch.zeros(2, dtype=torch.float32, device=DEV)
+    dabs.dabs_mlp_grad(untrained, f_te.shape[0], f_te, y_te, None, loss[0:1])
+    dabs.dabs_mlp_grad(net, f_te.shape[0], f_te, y_te, None, loss[1:2])
+    torch.cuda.synchronize()
+    before, after = loss.cpu().numpy()
+    assert hist[-1] < hist[0]
+    assert after < before and after < np.log(2.0), (before, after)

@@ -132,3 +132,14 @@ def test_operations():
                          for r in range(8)])
         assert abs(flips - rate) < 0.02, (zval, flips, rate)
     assert list(mlp.mutate_level(np.array([0.03125, 0.09375, -0.03125, 8.1, -9.0], np.float32))) == [0, 2, 0, 127, -128]
+
+
+def test_labels_symmetric_closed_forms():
+    ref = np.array([1, 0, 1, 1, 0, 0, 1, 0], np.uint8)
+    assert list(mlp.labels(ref, ref)) == [0] * 8
+    assert list(mlp.labels(1 - ref, ref)) == [1] * 8
+    assert list(mlp.labels(1 - ref, ref, symmetric=True)) == [0] * 8      # the complement is the same cut
+    x = ref.copy(); x[:4] ^= 1                                            # distance 4 = n/2: ties keep ref
+    assert list(mlp.labels(x, ref, symmetric=True)) == [1, 1, 1, 1, 0, 0, 0, 0]
+    x[4] ^= 1                                                             # distance 5 > n/2: complement
+    assert list(mlp.labels(x, ref, symmetric=True)) == [0, 0, 0, 0, 0, 1, 1, 1]
