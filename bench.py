@@ -43,12 +43,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_items_maxcut800_traffic.js
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources and headers the search kernels are built from."""
-    import glob
+    """sha256 over the sources the batch-search kernel is built from."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2207_03069_amd", "csrc", "*")))
-    for f in files + [os.path.join(ROOT, "include", "dabs.h")]:
+    csrc = os.path.join(ROOT, "paper_2207_03069_amd", "csrc")
+    for f in [os.path.join(csrc, x) for x in ("dabs_walk.hip", "dabs_walker.h", "dabs_device.h", "dabs_internal.h")]:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
