@@ -18,6 +18,15 @@
  * pairs (i,j), W symmetric -- Section II, Eq. (2), whose index set E u VxV is
  * the whole of VxV.  Table III's QUBO optima equal C - n p only under this
  * full sum.  Hence the per-pair update of Eq. (4) carries a factor 2.
+ *
+ * Pins: energies, deltas, Greedy, Straight, TwoNeighbor, tabu-greedy,
+ * CyclicMin, Step 1, the batch schedule, rank selection, the genetic
+ * operations and the pools are pinned by the tests against scratch energies,
+ * brute force, printed examples and closed forms.  The random choices of
+ * MaxMin, PositiveMin and RandomMin (which candidate a draw selects) are
+ * parity unpinned: tests pin only their properties (threshold ranges,
+ * candidate sets, the argmin at t = T); the exact choice is fixed by the
+ * readings R6, R7, R9 and R18 and by agreement with the device.
  */
 #include <stdint.h>
 #include <stdlib.h>
