@@ -203,11 +203,18 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
         const int64_t e = b.best_e[gi];
         if (!(e < se[m - 1])) continue;
         const uint64_t *bits = b.best + d.inst_word0 + (int64_t)i * nw;
+        // an identical vector has the same energy, unless the entry is one of
+        // the initial random vectors (energy +inf, never evaluated): only
+        // those entries are compared bit for bit, one entry per lane
         bool dup = false;
-        for (int r = 0; r < m && !dup; ++r) {
-            bool diff = false;
-            for (int w = lane; w < nw; w += WAVE) diff |= pbits[(int64_t)r * nw + w] != bits[w];
-            dup = __builtin_amdgcn_ballot_w64(diff) == 0;
+        for (int r0 = 0; r0 < m && !dup; r0 += WAVE) {
+            const int r = r0 + lane;
+            bool same = false;
+            if (r < m && (se[r] == e || se[r] == E_INF)) {
+                same = true;
+                for (int w = 0; w < nw; ++w) same = same && pbits[(int64_t)r * nw + w] == bits[w];
+            }
+            dup = __builtin_amdgcn_ballot_w64(same) != 0;
         }
         if (dup) continue;
         int pos = 0;
@@ -460,7 +467,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
 // One round on stream st: targets, batch searches (one launch per size
 // class; classes run on parallel streams), packet insertion, round++.
 static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturing) {
-    if (s->mlp)
+    if (s->mlp && s->mlp_ops)         // pools are scored only when an MLP operation can be chosen
         for (int p = 0; p < s->nprob; ++p) {
             const ProbDesc &d = s->hdesc[p];
             const int r = mlp_pool_logits(s->probs[p], s->mlp, s->d.pool_bits + d.pool_word0, d.g.npools,
@@ -652,7 +659,7 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
     };
     copy(sx, s->d.x, xw); copy(sb, s->d.best, xw); copy(se, s->d.e, i8); copy(sbe, s->d.best_e, i8);
     copy(sph, s->d.ph, i4); copy(sc, s->d.ctr, 8);
-    if (status == DABS_OK && s->mlp)
+    if (status == DABS_OK && s->mlp && s->mlp_ops)
         for (int p = 0; p < s->nprob && status == DABS_OK; ++p) {
             const ProbDesc &d = s->hdesc[p];
             status = mlp_pool_logits(s->probs[p], s->mlp, s->d.pool_bits + d.pool_word0, d.g.npools, d.g.capacity,

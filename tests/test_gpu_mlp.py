@@ -231,8 +231,8 @@ def test_solver_with_learned_operations_exact_energies():
 
 
 def test_solver_with_network_attached_but_plain_operations_is_exact():
-    """Scoring the pools every round changes nothing while the learned
-    operations are disabled: bit-exact with the oracle."""
+    """Attaching a network changes nothing while the learned operations are
+    disabled: bit-exact with the oracle."""
     n = 70
     W = inputs.dense_qubo(n, -100, 100, 2)
     bits, pe, po, x, e, g = solver_with_mlp(W, tuple(range(8)), 3)
