@@ -218,6 +218,60 @@ def learned_vs_plain(dev, n=2000, instances=256, npools=4, capacity=50, ref_roun
             "plain": res["plain"], "learned": res["learned"]}
 
 
+def tsp_quality(dev, rounds=8, ncity=32):
+    """Configuration 3: 32 cities uniform in [0, 999]^2, one-hot encoding
+    n = 1024 (bit c*N + t: city c at position t), dense int32 W, A = 2 max d;
+    8192 instances, 8 pools x 100, two-point crossover, 1 % mutation, s = 0.1,
+    b = 1.  Reports the best energy after `rounds` rounds, whether the best
+    vector is a tour, its length (E = 2L - 2NA for a tour) and, for context,
+    the nearest-neighbour tour length."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    W, D, A = inputs.tsp_instance(ncity, seed=0)
+    n = W.shape[0]
+    prob = dabs.dabs_problem_create(torch.from_numpy(W).to(dev))
+    g = dabs.ga_params(T=round(0.1 * n), Bn=n, tau=TAU, seed=0, capacity=100, npools=8, crossover_kind=1,
+                       p_mutation=42949673)
+    inst = 8192
+    s = dabs.dabs_solver_create(prob, g, inst)
+    dabs.dabs_solver_autotune(s)
+    tot = torch.zeros(1, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dabs.dabs_solver_run(s, rounds)
+    dabs.dabs_solver_state(s, total_flips=tot)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nw = (n + 63) // 64
+    bits = torch.zeros((8, 100, nw), dtype=torch.int64, device=dev)
+    pe = torch.zeros((8, 100), dtype=torch.int64, device=dev)
+    dabs.dabs_solver_pools(s, bits, pe)
+    torch.cuda.synchronize()
+    pe_h = pe.cpu().numpy()
+    q = int(np.argmin(pe_h[:, 0]))
+    x = inputs.unpack_bits(bits[q, 0:1].cpu().numpy().view(np.uint64), n)[0].reshape(ncity, ncity)
+    tour_ok = bool((x.sum(axis=0) == 1).all() and (x.sum(axis=1) == 1).all())
+    length = None
+    if tour_ok:
+        order = [int(np.argmax(x[:, t])) for t in range(ncity)]
+        length = int(sum(D[order[t], order[(t + 1) % ncity]] for t in range(ncity)))
+    # nearest-neighbour tour from city 0 (host, context only)
+    left, cur, nn = set(range(1, ncity)), 0, 0
+    while left:
+        nxt = min(left, key=lambda c: (D[cur, c], c))
+        nn += int(D[cur, nxt])
+        left.remove(nxt)
+        cur = nxt
+    nn += int(D[cur, 0])
+    best_e = int(pe_h[q, 0])
+    return {"workload": "TSP 32 cities -> one-hot QUBO n=1024, int32 W, A=2*max d=%d; 8192 instances, "
+                        "8 pools x 100, two-point crossover, 1%% mutation, s=0.1 b=1" % A,
+            "rounds": rounds, "wall_s": wall, "flips": int(tot.item()), "flips_per_s": int(tot.item()) / wall,
+            "best_energy": best_e, "best_is_tour": tour_ok, "tour_length": length,
+            "energy_check": (best_e == 2 * length - 2 * ncity * A) if tour_ok else None,
+            "nearest_neighbour_length": nn}
+
+
 def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
     """The many-problem workload: 256 dense int16 QUBOs, n log-uniform in
     [256, 4096), U[-1000, 1000].  Target of each problem: its best energy after
@@ -298,6 +352,7 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tsp", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 256 MiB device copy")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -379,6 +434,10 @@ def main():
     if not args.no_learned:
         print("bench: learned vs plain ...", file=sys.stderr, flush=True)
         learned = learned_vs_plain(dev)
+    tsp = None
+    if not args.no_tsp:
+        print("bench: TSP ...", file=sys.stderr, flush=True)
+        tsp = tsp_quality(dev)
     batched = None
     if not args.no_batched:
         print("bench: batched vs one problem at a time ...", file=sys.stderr, flush=True)
@@ -397,6 +456,7 @@ def main():
         "time_to_target": tts,
         "time_to_target_learned_vs_plain": learned,
         "time_to_target_batched_vs_single": batched,
+        "tsp": tsp,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

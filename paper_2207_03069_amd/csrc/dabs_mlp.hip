@@ -286,15 +286,26 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
     }
 }
 
-// grad[i] = sum over blocks of part[b][i] (block order); loss = mean.
-__global__ void k_mlp_reduce(const float *__restrict__ part, int blocks, float invN, float *__restrict__ grad,
-                             float *__restrict__ loss) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > NPAR) return;
+// grad[i] = sum over blocks of part[b][i]; loss = mean.  A workgroup of 1024
+// threads covers 64 values: 16 groups sum the blocks b = g, g + 16, ... and
+// the 16 group sums are added in group order (a fixed order: reproducible).
+constexpr int RED_COLS = 64, RED_GROUPS = 16;
+__global__ __launch_bounds__(1024) void k_mlp_reduce(const float *__restrict__ part, int blocks, float invN,
+                                                     float *__restrict__ grad, float *__restrict__ loss) {
+    __shared__ float acc[RED_GROUPS][RED_COLS];
+    const int c = (int)threadIdx.x % RED_COLS, g = (int)threadIdx.x / RED_COLS;
+    const int i = blockIdx.x * RED_COLS + c;
     float s = 0.f;
-    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * (NPAR + 1) + i];
-    if (i < NPAR) grad[i] = s;
-    else if (loss) *loss = s * invN;
+    if (i <= NPAR)
+        for (int b = g; b < blocks; b += RED_GROUPS) s += part[(int64_t)b * (NPAR + 1) + i];
+    acc[g][c] = s;
+    __syncthreads();
+    if (g == 0 && i <= NPAR) {
+        float t = 0.f;
+        for (int q = 0; q < RED_GROUPS; ++q) t += acc[q][c];
+        if (i < NPAR) grad[i] = t;
+        else if (loss) *loss = t * invN;
+    }
 }
 
 // Adam (Kingma & Ba) on the float32 master copy; c1 = 1/(1-b1^t),
@@ -538,8 +549,8 @@ int dabs_mlp_grad(dabs_mlp *s, int64_t count, const uint16_t *feat_dev, const ui
     hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(64), 0, st, s->wbf, s->par, (const short *)feat_dev, labels_dev,
                        count, invN, s->part);
     HIP_OK(hipGetLastError());
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((NPAR + 1 + 255) / 256), dim3(256), 0, st, s->part, blocks, invN, s->grad,
-                       s->loss);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NPAR + 1 + RED_COLS - 1) / RED_COLS), dim3(RED_COLS * RED_GROUPS), 0, st,
+                       s->part, blocks, invN, s->grad, s->loss);
     HIP_OK(hipGetLastError());
     if (grad_dev) HIP_OK(hipMemcpyAsync(grad_dev, s->grad, sizeof(float) * NPAR, hipMemcpyDeviceToDevice, st));
     if (loss_dev) HIP_OK(hipMemcpyAsync(loss_dev, s->loss, sizeof(float), hipMemcpyDeviceToDevice, st));
