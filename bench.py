@@ -94,18 +94,19 @@ def _oracle_worker(args):
 
 def cpu_baseline(W, T, Bn):
     """The CPU oracle on the host cores: independent processes, each one
-    generational round of 16 instances of the same workload (distinct seeds)."""
+    generational round of 32 instances of the same workload (distinct seeds),
+    about 20 s of CPU work in all."""
     import oracle
     oracle.build(force=False)
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    jobs = [(W, T, Bn, 16, SEED + 1 + k) for k in range(cores)]
+    jobs = [(W, T, Bn, 32, SEED + 1 + k) for k in range(cores)]
     ctx = mp.get_context("fork")          # no GPU has been touched yet in this process
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         flips = sum(pool.map(_oracle_worker, jobs))
     dt = time.perf_counter() - t0
     return {"value": flips / dt, "unit": "flips/s", "cores": cores, "kind": "oracle",
-            "sample": "%d processes x (16 instances x 1 generational round), %d flips in %.1f s" %
+            "sample": "%d processes x (32 instances x 1 generational round), %d flips in %.1f s" %
                       (cores, flips, dt)}
 
 
@@ -129,7 +130,7 @@ def _first_hits(solver_run, progress, rounds_cap, nprob, dev):
 
 
 def learned_vs_plain(dev, n=2000, instances=256, npools=4, capacity=50, ref_rounds=100, cap=300,
-                     collect_rounds=500, seeds=(1, 2, 3, 4, 5)):
+                     collect_rounds=500, seeds=(1, 2, 3, 4, 5), epochs=2, lr=2e-3):
     """Time to target of the plain DABS loop and of the loop with the learned
     operations on a K2000-like max-cut (complete graph, n = 2000, +-1 weights,
     seed 0), after training the network on 10^5 pool solutions of a plain run
@@ -153,7 +154,7 @@ def learned_vs_plain(dev, n=2000, instances=256, npools=4, capacity=50, ref_roun
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
     t1 = time.perf_counter()
-    net, hist = train.fit(feats, labels, epochs=2, batch=1 << 16, lr=2e-3, seed=0)
+    net, hist = train.fit(feats, labels, epochs=epochs, batch=1 << 16, lr=lr, seed=0)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     nsamp = int(feats.shape[0])
