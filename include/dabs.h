@@ -81,11 +81,13 @@ int32_t dabs_max_n(int32_t wtype);
  *          DABS_W_I16) or int32 (DABS_W_I32) with row stride ld >= n elements.
  * The library validates W on the device (symmetry; delta bound
  * B = max_k |W_kk| + 2 sum_{j!=k} |W_kj| < 2^23 - 1, which keeps every delta and
- * local field exact in the device representation), then copies it into its
- * own padded layout.  This call synchronises `stream` once (validation
+ * local field exact in the device representation; int16 weights off the
+ * diagonal in [-32767, 32767], since the search negates them in 16 bits),
+ * then copies it into its own padded layout.  This call synchronises `stream` once (validation
  * result); the caller may free w_dev afterwards.
  * Errors: DABS_E_INVALID (null, n < 1, ld < n, bad wtype), DABS_E_UNSUPPORTED
- * (n > dabs_max_n), DABS_E_NOT_SYMMETRIC, DABS_E_RANGE (B >= 2^23 - 1),
+ * (n > dabs_max_n), DABS_E_NOT_SYMMETRIC, DABS_E_RANGE (B >= 2^23 - 1, or an
+ * int16 -32768 off the diagonal),
  * DABS_E_NOMEM, DABS_E_HIP.  *out is set only on success.
  */
 int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,

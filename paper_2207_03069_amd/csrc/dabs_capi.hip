@@ -28,7 +28,8 @@ namespace dabs {
 
 // Symmetry and delta bound of the caller's W: one block per row i; every
 // thread compares its W_ij with W_ji and sums |W_ij| (counted twice off the
-// diagonal).
+// diagonal).  bad: bit 0 asymmetric, bit 1 an int16 -32768 off the diagonal
+// (the search negates off-diagonal int16 weights in 16 bits).
 template <typename WT>
 __global__ __launch_bounds__(256) void k_validate(const WT *__restrict__ W, int64_t ld, int n,
                                                   int *__restrict__ bad, long long *__restrict__ rowb) {
@@ -38,6 +39,7 @@ __global__ __launch_bounds__(256) void k_validate(const WT *__restrict__ W, int6
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const long long a = W[(int64_t)i * ld + j], b = W[(int64_t)j * ld + i];
         asym |= a != b;
+        if (sizeof(WT) == 2 && j != i && a == -32768) asym |= 2;
         acc += (j == i ? 1 : 2) * (a < 0 ? -a : a);
     }
     __shared__ long long part[256];
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(256) void k_validate(const WT *__restrict__ W, int6
     }
     if (threadIdx.x == 0) {
         rowb[i] = part[0];
-        if (pbad[0]) atomicOr(bad, 1);
+        if (pbad[0]) atomicOr(bad, pbad[0]);
     }
 }
 
@@ -164,7 +166,9 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     long long bound = 0;
     for (int i = 0; i < n && status == DABS_OK; ++i) bound = hb[i] > bound ? hb[i] : bound;
     free(hb);
-    if (status == DABS_OK && hbad) status = dabs_fail(DABS_E_NOT_SYMMETRIC, "W is not symmetric");
+    if (status == DABS_OK && (hbad & 1)) status = dabs_fail(DABS_E_NOT_SYMMETRIC, "W is not symmetric");
+    if (status == DABS_OK && (hbad & 2))
+        status = dabs_fail(DABS_E_RANGE, "int16 W holds -32768 off the diagonal (pass it as int32)");
     if (status == DABS_OK && bound >= (1 << 23) - 1)
         status = dabs_fail(DABS_E_RANGE, "delta bound %lld >= 2^23 - 1", bound);
     if (status == DABS_OK) {

@@ -11,8 +11,8 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     const int wid = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     if (wid >= a.count) return;                       // whole wave leaves together
     typedef typename Walker<WT, SLOTS>::vecE vecE;
-    vecE h, s2, ex, key;
-    Walker<WT, SLOTS> w(h, s2, ex, key);
+    vecE kb, mul;
+    Walker<WT, SLOTS> w(kb, mul);
     w.setup((const WT *)a.W, a.diag, a.ld, a.n, a.seed, a.inst0 + (uint32_t)wid);
     uint64_t *x = a.x + (int64_t)wid * a.nwords;
     w.load_x(x);
@@ -61,13 +61,13 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 template <typename WT, int SLOTS, int WPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_walk_items(ItemsArgs a) {
     typedef typename Walker<WT, SLOTS>::vecE vecE;
-    vecE h, s2, ex, key;
+    vecE kb, mul;
     const int lane = lane_id();
     const BatchDev &b = a.b;
     const int2 item = a.items[blockIdx.x];
     const int p = __builtin_amdgcn_readfirstlane(item.x), i = __builtin_amdgcn_readfirstlane(item.y);
     ProbDesc *d = b.desc + p;
-    Walker<WT, SLOTS> w(h, s2, ex, key);
+    Walker<WT, SLOTS> w(kb, mul);
     w.setup((const WT *)d->W, d->diag, d->ld, d->n, d->g.seed, (uint32_t)i);
     const int64_t gi = d->inst0 + i;
     const int64_t wo = d->inst_word0 + (int64_t)i * d->nw;

@@ -1,25 +1,39 @@
 // dabs_walker.h -- one search instance per wavefront (Section III-A, B).
 //
-// The walker keeps X, the local fields, BEST and the energies of one instance
-// in the registers of one wave (layout in dabs_device.h).  Every flip reads
-// one row of W (16-byte loads, one per slot) and updates the local fields with
-// one v_dot2 (int16) or v_mad_i32_i24 (int32) per element; the argmin over
-// the deltas is a per-lane min3 chain over packed (delta, index) keys followed
-// by a DPP wave reduction.  Step 1 (BEST) runs at every visited state.
+// The walker keeps X, the deltas, BEST and the energies of one instance in
+// the registers of one wave (layout in dabs_device.h).  Every element holds
+// one word, its biased key
+//     kb_j = Delta_j 2^KB + j + 2^29  (+ 2^31 while the element is excluded),
+// which orders the elements of a lane by (Delta, index) and is updated in
+// place on every flip (Eq. (4)): kb_j += 2 (1 - 2 x_i)(1 - 2 x_j) W_ij 2^KB,
+// one v_dot2 (int16) or 24-bit multiply-add (int32) per element with a
+// per-element multiplier word mul_j = (1 - 2 x_j) 2^(KB+1).
 //
-// Rule domains (tabu, Straight's differing bits, padding) are expressed with
-// one integer per element, ex[j]: element j is outside the domain of
-// iteration t when ex[j] >= t.  Tabu sets ex[j] = t0 + tau when bit j flips
-// at iteration t0 (so it is excluded at t0+1 .. t0+tau and expires by
-// itself); padding elements hold EX_ALWAYS.  A masked key is one compare and
-// one v_cndmask per element.
+// Exclusions (tabu, Straight's settled bits, padding) are the sign bit, so
+// that the rule domains cost no per-element test:
+//   least key of the domain  = unsigned minimum (excluded words are >= 2^31);
+//   greatest key of the domain = signed maximum (excluded words are negative);
+//   least key of all bits     = per lane min(unsigned min, signed min & ~2^31),
+//     since the signed minimum of a lane is its least excluded word when it
+//     has one.
+// Valid keys lie in (-2^29, 2^29) (|Delta| < 2^23, KB <= 6), so valid
+// unexcluded words lie in (0, 2^30) and anything at or above 2^30 is "none".
+// The tabu of R11 (bit flipped at iteration t excluded at t+1 .. t+tau) is
+// set on the flip and cleared tau+1 iterations later from a 32-entry ring
+// held in one register (lane r: the bit flipped at iteration t = r mod 32).
+// Step 1 (BEST) runs at every visited state.
 #pragma once
 #include "dabs_device.h"
 
 namespace dabs {
 
-constexpr int EX_NEVER = -(1 << 30);
-constexpr int EX_ALWAYS = 0x7fffffff;
+constexpr int KBIAS = 1 << 29;
+constexpr uint32_t XBIT = 0x80000000u;
+// padding element: excluded, and above every key once the sign is cleared
+constexpr int KB_PAD = (int)0xFFFFFFF0u;
+// masked-out value in unsigned minima (not 0xFFFFFFFF: with the all-ones
+// value the compiler turns select + min3 into a min followed by a select)
+constexpr uint32_t UOUT = 0xFFFFFFF0u;
 
 struct Sel {
     int d;   // delta of the selected bit
@@ -46,16 +60,24 @@ struct Walker {
     static constexpr int KB = clog2(EPL) < LOGV ? LOGV : clog2(EPL);
     static constexpr int SB = KB - LOGV;
     static constexpr int SPAN = WAVE * V;   // bits covered by one slot
+    // wave reductions run on kb >> LOGV (key order down to the slot; the lane
+    // comes from a ballot and the sub-index from that lane's word)
+    static constexpr int BIAS_W = KBIAS >> LOGV;
+    static constexpr int NONE_W = (1 << 30) >> LOGV;
+    // multiplier of an element with x = 0, and the mask that negates one
+    // (int16: the element's 16-bit half of the dot2 operand, the other half 0)
+    static constexpr int MUL0 = 1 << (KB + 1);
+    static constexpr uint32_t MFLIP =
+        sizeof(WT) == 2 ? ((0x10000u - (1u << (KB + 2))) & 0xFFFFu) : (uint32_t)(-(1 << (KB + 2)));
     typedef int vecE __attribute__((ext_vector_type(EPL)));
 
     // The per-element vectors are the kernel's own local variables, one flat
     // vector each (element j = s*V + e), which keeps them in registers and
     // turns a uniform dynamic index into s_set_gpr_idx; the walker refers to
     // them.
-    vecE &h, &s2, &ex, &key;
+    vecE &kb, &mul;
 
-    __device__ __forceinline__ Walker(vecE &h_, vecE &s2_, vecE &ex_, vecE &key_)
-        : h(h_), s2(s2_), ex(ex_), key(key_) {}
+    __device__ __forceinline__ Walker(vecE &kb_, vecE &mul_) : kb(kb_), mul(mul_) {}
 
     const WT *__restrict__ W;
     int64_t ld;
@@ -63,9 +85,11 @@ struct Walker {
     uint64_t xb, bb;          // X and BEST bits of this lane (bit j)
     uint64_t vb;              // valid-element bits of this lane (bit j set iff bit index < n)
     int64_t E, Eb;
-    // Step 1 state of the current vector: per-lane unmasked minimum key and
-    // its wave minimum (key >> LOGV)
-    int kminU, mU;
+    int ring;                 // tabu ring (see above); -1: nothing to clear
+    // Step 1 state of the current vector: per-lane least word over all bits
+    // and its wave minimum (as kb >> LOGV)
+    uint32_t kminU;
+    int mU;
     // time to target
     int64_t target;
     unsigned long long *hit;
@@ -90,14 +114,13 @@ struct Walker {
         for (int ss = 0; ss < SLOTS; ++ss)
             if (ss == s) f(ss);
     }
-    __device__ __forceinline__ void set_lane_elem(vecE &a, int j, int L, int v) {
-        const int o = a[j];
-        a[j] = lane == L ? v : o;
-    }
-    __device__ __forceinline__ void neg_lane_elem(vecE &a, int j, int L) {
-        const int o = a[j];
-        a[j] = lane == L ? -o : o;
-    }
+
+    // ---------------------------------------------------------------- decoding
+    static __device__ __forceinline__ int wv(uint32_t u) { return (int)(u >> LOGV); }
+    static __device__ __forceinline__ bool none(int m) { return m >= NONE_W; }
+    // delta of a wave value / of an element's word
+    static __device__ __forceinline__ int dlt_w(int m) { return (m - BIAS_W) >> SB; }
+    static __device__ __forceinline__ int dlt_k(int k) { return ((k & 0x7FFFFFFF) - KBIAS) >> KB; }
 
     // ------------------------------------------------------------- set up
     __device__ __forceinline__ void setup(const WT *Wp, const int *diag, int64_t ld_, int n_, uint64_t seed_,
@@ -109,40 +132,42 @@ struct Walker {
         for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
             for (int e = 0; e < V; ++e) {
+                const int j = s * V + e;
                 const int k = gidx(s, e);
-                if (k < n) vb |= 1ull << (s * V + e);
-                h[s * V + e] = k < n ? diag[k] : H_PAD;      // X = 0: Delta_k = W_kk
-                s2[s * V + e] = 1 << KB;
-                ex[s * V + e] = k < n ? EX_NEVER : EX_ALWAYS;
+                if (k < n) vb |= 1ull << j;
+                kb[j] = k < n ? diag[k] * (1 << KB) + j + KBIAS : KB_PAD;   // X = 0: Delta_k = W_kk
+                mul[j] = (sizeof(WT) == 2 && (j & 1)) ? (int)((uint32_t)MUL0 << 16) : MUL0;
             }
         xb = 0; bb = 0; E = 0; Eb = 0;
+        ring = -1;
         hit = nullptr; hit_done = true; target = 0; t0 = 0;
         trace = nullptr; trace_cap = 0; flips = 0;
     }
 
-    __device__ __forceinline__ void ex_reset() {
-#pragma unroll
-        for (int j = 0; j < EPL; ++j) ex[j] = ((vb >> j) & 1) ? EX_NEVER : EX_ALWAYS;
-    }
-
-    // h_k += c W_ik for all k (row i of the zero-diagonal copy of W).  The
-    // padded rows hold zeros, so every lane loads every slot.
-    __device__ __forceinline__ void update_row(int i, int c) {
+    // kb_k += 2 y_i y_k W_ik 2^KB for all k (row i of the zero-diagonal copy
+    // of W, y = 1 - 2x).  The padded rows hold zeros, so every lane loads
+    // every slot.  int16: y_i W is one packed 16-bit multiply per word (the
+    // library rejects -32768 in int16 W, so the negation is exact).
+    __device__ __forceinline__ void update_row(int i, int yi) {
         if ((unsigned)i >= (unsigned)n) i = 0;     // never read outside W (a selection bug shows in parity)
         const WT *row = W + (int64_t)i * ld + lane * V;
         uint4 q[SLOTS];
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) q[s] = *(const uint4 *)(row + s * SPAN);
         if constexpr (sizeof(WT) == 2) {
-            const short2v clo = {(short)c, 0}, chi = {0, (short)c};
+            const short2v y2 = {(short)yi, (short)yi};
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
                 const uint32_t d[4] = {q[s].x, q[s].y, q[s].z, q[s].w};
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    const short2v w2 = __builtin_bit_cast(short2v, d[p]);
-                    h[s * V + 2 * p] = __builtin_amdgcn_sdot2(w2, clo, h[s * V + 2 * p], false);
-                    h[s * V + 2 * p + 1] = __builtin_amdgcn_sdot2(w2, chi, h[s * V + 2 * p + 1], false);
+                    const short2v w2 = __builtin_bit_cast(short2v, d[p]) * y2;
+                    const int j = s * V + 2 * p;
+                    // (element values first: a bit cast of a vector element
+                    // expression would read the vector's first element)
+                    const int m0 = mul[j], m1 = mul[j + 1];
+                    kb[j] = __builtin_amdgcn_sdot2(w2, __builtin_bit_cast(short2v, m0), kb[j], false);
+                    kb[j + 1] = __builtin_amdgcn_sdot2(w2, __builtin_bit_cast(short2v, m1), kb[j + 1], false);
                 }
             }
         } else {
@@ -150,20 +175,35 @@ struct Walker {
             for (int s = 0; s < SLOTS; ++s) {
                 const uint32_t d[4] = {q[s].x, q[s].y, q[s].z, q[s].w};
 #pragma unroll
-                for (int p = 0; p < 4; ++p) h[s * V + p] = mad24((int)d[p], c, h[s * V + p]);
+                for (int p = 0; p < 4; ++p) {
+                    const int j = s * V + p;
+                    kb[j] = mad24(mad24((int)d[p], yi, 0), mul[j], kb[j]);
+                }
             }
         }
     }
 
-    // Flip bit i of X without Step 1 (set-up walk from X = 0).
-    __device__ __forceinline__ void raw_flip(int i) {
-        const int L = lidx_to_lane(i), j = lidx_of(i);
-        const int xi = (int)((readlane64(xb, L) >> j) & 1);
-        const int hi = readlane(h[j], L);
-        E += xi ? -hi : hi;
-        update_row(i, xi ? -2 : 2);
-        neg_lane_elem(s2, j, L);
-        xb ^= lane == L ? (1ull << j) : 0ull;
+    // Flip the (uniform) selected bit: every word by Eq. (4), the bit's own
+    // word by Eq. (5) (its key k becomes 2j - k; the exclusion bit is kept
+    // because 2 * 2^31 vanishes mod 2^32), its multiplier negated.
+    __device__ __forceinline__ void flip_bit(const Sel &s) {
+        const bool xi = (readlane64(xb, s.L) >> s.j) & 1;
+        update_row(s.i, xi ? -1 : 1);
+        const int o = kb[s.j];
+        kb[s.j] = lane == s.L ? (2 * s.j + 2 * KBIAS) - o : o;
+        const int mo = mul[s.j];
+        const uint32_t mf = (sizeof(WT) == 2 && (s.j & 1)) ? (MFLIP << 16) : MFLIP;
+        mul[s.j] = lane == s.L ? (int)((uint32_t)mo ^ mf) : mo;
+        xb ^= lane == s.L ? (1ull << s.j) : 0ull;
+    }
+
+    __device__ __forceinline__ Sel sel_of(int i) {
+        Sel s;
+        s.i = i;
+        s.L = lidx_to_lane(i);
+        s.j = lidx_of(i);
+        s.d = dlt_k(readlane(kb[s.j], s.L));
+        return s;
     }
 
     // X := x (packed words), walking from X = 0 by flips in increasing index.
@@ -175,7 +215,9 @@ struct Walker {
             while (word) {
                 const int b = __builtin_ctzll(word);
                 word &= word - 1;
-                raw_flip(w * 64 + b);
+                const Sel s = uniform(sel_of(w * 64 + b));
+                E += s.d;
+                flip_bit(s);
             }
         }
     }
@@ -199,62 +241,44 @@ struct Walker {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int k = gidx(s, e);
-                if (k < n) out[k] = s2[s * V + e] > 0 ? h[s * V + e] : -h[s * V + e];
+                if (k < n) out[k] = dlt_k(kb[s * V + e]);
             }
     }
 
-    // ------------------------------------------------------------- keys
-    // key_j = Delta_j 2^KB + j.  Up to 32 elements per lane the keys are kept
-    // in registers after each flip; above that they are recomputed where used
-    // (one multiply-add), which keeps the walker within the register file.
-    static constexpr bool KEEP = EPL <= 32;
-    __device__ __forceinline__ int K(int j) const {
-        if constexpr (KEEP) return key[j];
-        else return mad24(h[j], s2[j], j);
-    }
-    __device__ __forceinline__ void compute_keys() {
-        if constexpr (KEEP) {
+    // ------------------------------------------------------------- reductions
+    __device__ __forceinline__ uint32_t lane_umin() const {
+        uint32_t m = UOUT;
 #pragma unroll
-            for (int j = 0; j < EPL; ++j) key[j] = mad24(h[j], s2[j], j);
-        }
-    }
-    __device__ __forceinline__ int lane_min_key() const {
-        int m = KEY_BIG;
-#pragma unroll
-        for (int j = 0; j < EPL; j += 2) m = min(m, min(K(j), K(j + 1)));
+        for (int j = 0; j < EPL; j += 2) m = min(m, min((uint32_t)kb[j], (uint32_t)kb[j + 1]));
         return m;
     }
-    // least key among elements with ex < thr (KEY_OUT when there is none)
-    __device__ __forceinline__ int lane_min_dom(int thr) const {
-        int m = KEY_OUT;
+    __device__ __forceinline__ int lane_smin() const {
+        int m = 0x7FFFFFFF;
 #pragma unroll
-        for (int j = 0; j < EPL; j += 2) {
-            const int a = ex[j] < thr ? K(j) : KEY_OUT;
-            const int b = ex[j + 1] < thr ? K(j + 1) : KEY_OUT;
-            m = min(m, min(a, b));
-        }
+        for (int j = 0; j < EPL; j += 2) m = min(m, min(kb[j], kb[j + 1]));
         return m;
+    }
+    // least word of all bits from the lane's unsigned and signed minima
+    static __device__ __forceinline__ uint32_t unmask(uint32_t um, int sm) {
+        return min(um, (uint32_t)sm & 0x7FFFFFFFu);
     }
 
-    // Wave argmin of per-lane minimum keys: lowest (delta, global index).
-    __device__ __forceinline__ Sel argmin_from(int kmin, int m) const {
-        const uint64_t bal = ballot((kmin >> LOGV) == m);
+    // Wave argmin of per-lane least words: lowest (delta, global index).
+    __device__ __forceinline__ Sel argmin_from(uint32_t kmin, int m) const {
+        const uint64_t bal = ballot(wv(kmin) == m);
         const int L = (int)__builtin_ctzll(bal);
-        const int kl = readlane(kmin, L);
+        const int kl = readlane((int)kmin, L);
         const int slot = m & ((1 << SB) - 1);
         Sel r;
-        r.d = m >> SB;
+        r.d = dlt_w(m);
         r.j = (slot << LOGV) | (kl & (V - 1));
         r.i = slot * SPAN + L * V + (kl & (V - 1));
         r.L = L;
         return r;
     }
-    __device__ __forceinline__ Sel wave_argmin(int kmin) const {
-        return argmin_from(kmin, wave_min(kmin >> LOGV));
+    __device__ __forceinline__ Sel wave_argmin(uint32_t kmin) const {
+        return argmin_from(kmin, wave_min(wv(kmin)));
     }
-    // wave minimum of k >> LOGV; the domain is empty when it decodes to a
-    // delta of H_PAD or more (only padding or excluded elements)
-    static __device__ __forceinline__ bool empty_dom(int m) { return (m >> SB) >= H_PAD; }
 
     __device__ __forceinline__ void note_best() {
         if (!hit_done && Eb <= target) {
@@ -266,7 +290,7 @@ struct Walker {
 
     // Step 1: BEST <- best 1-bit neighbour when strictly better than E(BEST).
     __device__ __forceinline__ void step1() {
-        const int d = mU >> SB;
+        const int d = dlt_w(mU);
         if (E + d < Eb) {
             const Sel s = argmin_from(kminU, mU);
             Eb = E + d;
@@ -275,52 +299,44 @@ struct Walker {
         }
     }
 
-    // Keys of the current state, then Step 1.
+    // Step 1 when nothing but padding is excluded.
     __device__ __forceinline__ void refresh() {
-        compute_keys();
-        kminU = lane_min_key();
-        mU = wave_min(kminU >> LOGV);
+        kminU = lane_umin();
+        mU = wave_min(wv(kminU));
         step1();
     }
-
-    // As refresh(), also reducing the least key of the domain ex < thr (kminM,
-    // mM) in the same pass.
-    int kminM, mM;
-    __device__ __forceinline__ void refresh_dom(int thr) {
-        compute_keys();
-        kminU = lane_min_key();
-        kminM = lane_min_dom(thr);
-        wave_min2(kminU >> LOGV, kminM >> LOGV, mU, mM);
+    // Step 1 while exclusions are in force.
+    __device__ __forceinline__ void refresh_all() {
+        kminU = unmask(lane_umin(), lane_smin());
+        mU = wave_min(wv(kminU));
         step1();
     }
-    // MaxMin's reductions of the domain ex < thr, made in the pass that
-    // recomputes the keys after a flip: least key kminM / mM (as
-    // refresh_dom) and greatest key mX (its wave maximum).
+    // As refresh_all(), also reducing the least word of the domain (kminM, mM)
+    // in the same pass.
+    uint32_t kminM;
+    int mM;
+    __device__ __forceinline__ void refresh_dom() {
+        const uint32_t um = lane_umin();
+        kminM = um;
+        kminU = unmask(um, lane_smin());
+        wave_min2(wv(kminU), wv(kminM), mU, mM);
+        step1();
+    }
+    // MaxMin's reductions: as refresh_dom's, and the domain's greatest word
+    // mX (signed maximum), all from one pass over the words.
     int mX;
-    __device__ __forceinline__ void dom_minmax(int thr) {
-        int ku = KEY_BIG, km = KEY_OUT, kx = -KEY_OUT;
+    __device__ __forceinline__ void dom_minmax() {
+        uint32_t um = UOUT;
+        int sm = 0x7FFFFFFF, sx = (int)0x80000000;
 #pragma unroll
         for (int j = 0; j < EPL; j += 2) {
-            const int k0 = K(j), k1 = K(j + 1);
-            const bool i0 = ex[j] < thr, i1 = ex[j + 1] < thr;
-            ku = min(ku, min(k0, k1));
-            km = min(km, min(i0 ? k0 : KEY_OUT, i1 ? k1 : KEY_OUT));
-            kx = max(kx, max(i0 ? k0 : -KEY_OUT, i1 ? k1 : -KEY_OUT));
+            um = min(um, min((uint32_t)kb[j], (uint32_t)kb[j + 1]));
+            sm = min(sm, min(kb[j], kb[j + 1]));
+            sx = max(sx, max(kb[j], kb[j + 1]));
         }
-        kminU = ku;
-        kminM = km;
-        wave_minmin_max(ku >> LOGV, km >> LOGV, kx, mU, mM, mX);
-    }
-    __device__ __forceinline__ void refresh_minmax(int thr) {
-        compute_keys();
-        dom_minmax(thr);
-        step1();
-    }
-
-    // argmin of the domain reduced by refresh_dom, or the plain argmin when
-    // the domain is empty
-    __device__ __forceinline__ Sel dom_sel() const {
-        return empty_dom(mM) ? argmin_from(kminU, mU) : argmin_from(kminM, mM);
+        kminM = um;
+        kminU = unmask(um, sm);
+        wave_minmin_max(wv(kminU), wv(kminM), sx, mU, mM, mX);
     }
 
     // BEST := X, then Step 1.
@@ -331,14 +347,11 @@ struct Walker {
         refresh();
     }
 
-    // Step 3: flip the selected bit, update E and every local field.
+    // Step 3: flip the selected bit, update E and every word.
     __device__ __forceinline__ void flip_core(const Sel &s0) {
         const Sel s = uniform(s0);
         E += s.d;
-        const bool xi = (readlane64(xb, s.L) >> s.j) & 1;
-        update_row(s.i, xi ? -2 : 2);
-        neg_lane_elem(s2, s.j, s.L);
-        xb ^= lane == s.L ? (1ull << s.j) : 0ull;
+        flip_bit(s);
         if (trace && flips < trace_cap && lane == 0) trace[flips] = s.i;
         flips++;
     }
@@ -346,35 +359,43 @@ struct Walker {
         flip_core(s);
         refresh();
     }
-    // flip, then refresh with the domain ex < thr of the next selection
-    __device__ __forceinline__ void flip_dom(const Sel &s, int thr) {
-        flip_core(s);
-        refresh_dom(thr);
+
+    // ------------------------------------------------------------- exclusions
+    __device__ __forceinline__ void mark(const Sel &s) {
+        const int o = kb[s.j];
+        kb[s.j] = lane == s.L ? (int)((uint32_t)o | XBIT) : o;
+    }
+    __device__ __forceinline__ void unmark(int j, int L) {
+        const int o = kb[j];
+        kb[j] = lane == L ? (o & 0x7FFFFFFF) : o;
+    }
+    // every valid bit back in the domain (padding stays out)
+    __device__ __forceinline__ void reset_marks() {
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) kb[j] = ((vb >> j) & 1) ? (kb[j] & 0x7FFFFFFF) : kb[j];
     }
 
-    __device__ __forceinline__ Sel sel_of(int i) {
-        Sel s;
-        s.i = i;
-        s.L = lidx_to_lane(i);
-        s.j = lidx_of(i);
-        s.d = readlane(K(s.j), s.L) >> KB;
-        return s;
-    }
-
-    // tabu (R11): bit flipped at iteration t is excluded at t+1 .. t+tau
-    // (one element write in every case: a conditional write would be turned
-    // into a select over the whole vector)
-    __device__ __forceinline__ void mark_tabu(const Sel &s0, int t, int tau) {
+    // Tabu (R11) of the bit flipped at iteration t.  maybe_marked: it was
+    // selected from an empty domain, so it may be excluded already; its
+    // pending release is then void (the new one replaces it).
+    __device__ __forceinline__ void tabu_mark(const Sel &s0, int t, int tau, bool maybe_marked) {
+        if (tau <= 0) return;
         const Sel s = uniform(s0);
-        const int o = ex[s.j];
-        ex[s.j] = (lane == s.L && tau > 0) ? t + tau : o;
+        const int e = (s.L << 8) | s.j;
+        if (maybe_marked && readlane(kb[s.j], s.L) < 0) {
+            for (int u = t - tau; u < t; ++u)
+                if (u >= 1 && readlane(ring, u & 31) == e) ring = lane == (u & 31) ? -1 : ring;
+        }
+        mark(s);
+        ring = lane == (t & 31) ? e : ring;
     }
-
-    // Non-tabu argmin of iteration t, or the plain argmin when every bit is tabu.
-    __device__ __forceinline__ Sel dom_argmin(int t) {
-        const int km = lane_min_dom(t);
-        const int m = wave_min(km >> LOGV);
-        return empty_dom(m) ? argmin_from(kminU, mU) : argmin_from(km, m);
+    // Before the domain of iteration t: the bit flipped at t - tau - 1 is back.
+    __device__ __forceinline__ void tabu_release(int t, int tau) {
+        const int t0r = t - tau - 1;
+        if (tau > 0 && t0r >= 1) {
+            const int e = readlane(ring, t0r & 31);
+            if (e >= 0) unmark(e & 255, e >> 8);
+        }
     }
 
     // ------------------------------------------------------------- rules
@@ -382,7 +403,7 @@ struct Walker {
     __device__ __forceinline__ int phase_greedy(int cap) {
         if (cap <= 0) cap = 64 * n;                   // documented default bound
         int f = 0;
-        while ((mU >> SB) < 0 && f < cap) {
+        while (dlt_w(mU) < 0 && f < cap) {
             flip(argmin_from(kminU, mU));
             f++;
         }
@@ -390,6 +411,7 @@ struct Walker {
     }
 
     // Straight (Section III-A.2): argmin over bits differing from the target.
+    // The bits that agree are excluded, and so is each bit once flipped.
     __device__ __forceinline__ int phase_straight(const uint64_t *target_bits) {
         const int nw = (n + 63) / 64;
         uint64_t db = 0;
@@ -406,19 +428,20 @@ struct Walker {
 #pragma unroll
         for (int j = 0; j < EPL; ++j) {
             const bool dif = (diff >> j) & 1;
-            ex[j] = dif ? EX_NEVER : EX_ALWAYS;
+            kb[j] = dif ? (kb[j] & 0x7FFFFFFF) : (int)((uint32_t)kb[j] | XBIT);
             hd += dif;
         }
         hd = (int)wave_sum64(hd);
-        kminM = lane_min_dom(0);
-        mM = wave_min(kminM >> LOGV);
+        kminM = lane_umin();
+        mM = wave_min(wv(kminM));
         int f = 0;
         for (; f < hd; ++f) {
             const Sel s = uniform(argmin_from(kminM, mM));
-            set_lane_elem(ex, s.j, s.L, EX_ALWAYS);
-            flip_dom(s, 0);
+            mark(s);
+            flip_core(s);
+            refresh_dom();
         }
-        ex_reset();
+        reset_marks();
         return f;
     }
 
@@ -429,11 +452,14 @@ struct Walker {
         kminM = kminU;            // iteration 1: nothing is tabu
         mM = mU;
         for (int t = 1; t <= T; ++t) {
-            const Sel s = dom_sel();
-            mark_tabu(s, t, tau);
-            flip_dom(s, t + 1);
+            const bool emp = none(mM);
+            const Sel s = emp ? argmin_from(kminU, mU) : argmin_from(kminM, mM);
+            tabu_mark(s, t, tau, emp);
+            flip_core(s);
+            tabu_release(t + 1, tau);
+            refresh_dom();
         }
-        ex_reset();
+        reset_marks();
         return T;
     }
 
@@ -453,45 +479,61 @@ struct Walker {
                 const int64_t ww = (int64_t)(((uint64_t)n * cube_frac(hh)) >> 32);
                 w = ww < c ? c : (ww > n ? n : (int)ww);
             }
+            tabu_release(t, tau);
             const bool wrap = pos + w > n;
             const int lo = wrap ? pos + w - n : pos;       // start of the excluded / included range
             const uint32_t span = wrap ? (uint32_t)(n - w) : (uint32_t)w;
-            int km = KEY_BIG, kw = KEY_BIG;
+            auto inwin = [&](int s, int e) {
+                const uint32_t off = (uint32_t)(gidx(s, e) - lo);
+                return wrap ? (off >= span) : (off < span);
+            };
+            uint32_t km = UOUT;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    const int j = s * V + e;
-                    const uint32_t off = (uint32_t)(gidx(s, e) - lo);
-                    const bool in = wrap ? (off >= span) : (off < span);
-                    km = min(km, in && ex[j] < t ? K(j) : KEY_BIG);
-                    kw = min(kw, in ? K(j) : KEY_BIG);
-                }
-            const int m = wave_min(km >> LOGV);
-            const Sel s = empty_dom(m) ? wave_argmin(kw) : argmin_from(km, m);
-            flip(s);
-            mark_tabu(s, t, tau);
+                for (int e = 0; e < V; ++e) km = min(km, inwin(s, e) ? (uint32_t)kb[s * V + e] : UOUT);
+            const int m = wave_min(wv(km));
+            const bool emp = none(m);
+            Sel s;
+            if (emp) {
+                // the window holds only tabu bits: the window without tabu
+                uint32_t kw = UOUT;
+#pragma unroll
+                for (int ss = 0; ss < SLOTS; ++ss)
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        kw = min(kw, inwin(ss, e) ? ((uint32_t)kb[ss * V + e] & 0x7FFFFFFFu) : UOUT);
+                s = wave_argmin(kw);
+            } else {
+                s = argmin_from(km, m);
+            }
+            flip_core(s);
+            refresh_all();
+            tabu_mark(s, t, tau, emp);
             pos = (pos + w) % n;
         }
-        ex_reset();
+        reset_marks();
         return T;
     }
 
-    // Candidates: elements of the domain (ex < thr) whose key is <= dk.
-    // Counts them, draws r = floor(v * count / 2^32) and returns the r-th
-    // candidate (0-based, in increasing bit index: slot, then lane, then
-    // sub-index).
-    __device__ __forceinline__ Sel pick_rth(int dk, int thr, uint32_t v) {
+    // Candidates: unexcluded elements (IGN: exclusions ignored, padding still
+    // out) whose key is <= dk.  Counts them, draws r = floor(v * count / 2^32)
+    // and returns the r-th candidate (0-based, in increasing bit index: slot,
+    // then lane, then sub-index).
+    template <bool IGN>
+    __device__ __forceinline__ Sel pick_rth(int dk, uint32_t v) {
+        const uint32_t lim = (uint32_t)(dk + KBIAS);
+        auto cand = [&](int j) {
+            const uint32_t k = IGN ? ((uint32_t)kb[j] & 0x7FFFFFFFu) : (uint32_t)kb[j];
+            return k <= lim;
+        };
         uint32_t cs[SLOTS];
         uint32_t c = 0;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
             cs[s] = 0;
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const int j = s * V + e;
-                cs[s] += (uint32_t)__builtin_popcountll(ballot(K(j) <= dk && ex[j] < thr));
-            }
+            for (int e = 0; e < V; ++e) cs[s] += (uint32_t)__builtin_popcountll(ballot(cand(s * V + e)));
             c += cs[s];
         }
         if (c == 0) return argmin_from(kminU, mU);   // cannot happen: the domain minimum qualifies
@@ -515,8 +557,7 @@ struct Walker {
             uint32_t excl = 0;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                const int j = ss * V + e;
-                cm[e] = ballot(K(j) <= dk && ex[j] < thr);
+                cm[e] = ballot(cand(ss * V + e));
                 cnt += __builtin_amdgcn_inverse_ballot_w64(cm[e]) ? 1 : 0;
                 excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm[e] >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)cm[e], excl));
@@ -537,42 +578,30 @@ struct Walker {
             out.j = ss * V + e_sel;
             out.i = ss * SPAN + L * V + e_sel;
         });
-        out.d = readlane(K(out.j), out.L) >> KB;
+        out.d = dlt_k(readlane(kb[out.j], out.L));
         return out;
-    }
-
-    // Domain threshold of iteration t: non-tabu bits, or every valid bit when
-    // all are tabu (R11); also returns the domain's least key.
-    __device__ __forceinline__ int domain(int t, int &km, int &mm) {
-        km = lane_min_dom(t);
-        mm = wave_min(km >> LOGV);
-        if (!empty_dom(mm)) return t;
-        km = kminU;
-        mm = mU;
-        return EX_ALWAYS;
     }
 
     // MaxMin (Section III-A.3).  The domain reductions of iteration t+1 (its
     // least and greatest key) are made by the refresh after the flip of
     // iteration t; the tabu mark of iteration t precedes that flip.
     __device__ __forceinline__ int phase_maxmin(int T, int tau, uint32_t ph) {
-        dom_minmax(1);                      // iteration 1: nothing is tabu
+        dom_minmax();                       // iteration 1: nothing is tabu
         FracStep fs;
         fs.init((uint32_t)T);
         R4 r = {{0u, 0u, 0u, 0u}};
         for (int t = 1; t <= T; ++t) {
             fs.next();
-            int thr = t;
-            if (empty_dom(mM)) {            // every bit tabu: tabu ignored (R11)
-                thr = EX_ALWAYS;
+            const bool ign = none(mM);      // every bit tabu: tabu ignored (R11)
+            if (ign) {
                 mM = mU;
-                int kx = -KEY_OUT;
+                int kx = (int)0x80000000;
 #pragma unroll
-                for (int j = 0; j < EPL; ++j) kx = max(kx, ex[j] < thr ? K(j) : -KEY_OUT);
+                for (int j = 0; j < EPL; ++j) kx = max(kx, ((vb >> j) & 1) ? (kb[j] & 0x7FFFFFFF) : (int)0x80000000);
                 mX = wave_max(kx);
             }
-            const int mind = mM >> SB;
-            const int maxd = mX >> KB;
+            const int mind = dlt_w(mM);
+            const int maxd = (mX - KBIAS) >> KB;
             // iterations 2c+1 and 2c+2 use words (0, 1) and (2, 3) of draw c (R18)
             if (!((t - 1) & 1)) r = philox((uint32_t)((t - 1) >> 1), inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
             const uint32_t u = ((t - 1) & 1) ? r.w[2] : r.w[0], v = ((t - 1) & 1) ? r.w[3] : r.w[1];
@@ -580,46 +609,50 @@ struct Walker {
             const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cube_frac(g)) >> 32;
             const int d = mind + (int)(((uint64_t)u * (span + 1)) >> 32);
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
-            const Sel s = pick_rth(dk, thr, v);
-            mark_tabu(s, t, tau);
+            const Sel s = ign ? pick_rth<true>(dk, v) : pick_rth<false>(dk, v);
+            tabu_mark(s, t, tau, ign);
             flip_core(s);
-            refresh_minmax(t + 1);
+            tabu_release(t + 1, tau);
+            dom_minmax();
+            step1();
         }
-        ex_reset();
+        reset_marks();
         return T;
     }
 
-    // PositiveMin (Section III-A.6).  Its domain's least key only decides
-    // whether the domain is empty; with n > tau at most tau bits are tabu, so
-    // it never is and that reduction is skipped.
+    // PositiveMin (Section III-A.6).  The least positive key of the domain is
+    // the unsigned minimum of kb - (2^29 + 2^KB): keys below 2^KB (delta <= 0)
+    // wrap to the top, excluded words stay above 2^30.  The domain can only be
+    // empty when n <= tau.
     __device__ __forceinline__ int phase_positivemin(int T, int tau, uint32_t ph) {
+        constexpr uint32_t C = (uint32_t)KBIAS + (1u << KB);
         const bool may_empty = n <= tau;
         R4 r = {{0u, 0u, 0u, 0u}};
         for (int t = 1; t <= T; ++t) {
-            int thr = t;
-            if (may_empty) {
-                int km, mm;
-                thr = domain(t, km, mm);
-            }
-            int kp = KEY_OUT;
+            tabu_release(t, tau);
+            bool ign = false;
+            if (may_empty) ign = none(wave_min(wv(lane_umin())));
+            uint32_t kp = UOUT;
+            if (!ign) {
 #pragma unroll
-            for (int j = 0; j < EPL; j += 2) {
-                const int a = (ex[j] < thr && K(j) >= (1 << KB)) ? K(j) : KEY_OUT;
-                const int b = (ex[j + 1] < thr && K(j + 1) >= (1 << KB)) ? K(j + 1) : KEY_OUT;
-                kp = min(kp, min(a, b));
+                for (int j = 0; j < EPL; j += 2) kp = min(kp, min((uint32_t)kb[j] - C, (uint32_t)kb[j + 1] - C));
+            } else {
+#pragma unroll
+                for (int j = 0; j < EPL; ++j) kp = min(kp, ((uint32_t)kb[j] & 0x7FFFFFFFu) - C);
             }
-            const int pd = wave_min(kp >> LOGV) >> SB;
-            const int d = pd >= H_PAD ? H_PAD - 1 : pd;
+            const int mw = wave_min(wv(kp));
+            const int d = none(mw) ? H_PAD - 1 : (mw >> SB) + 1;
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
             // iterations 4c+1 .. 4c+4 use words 0 .. 3 of draw c (R18)
             if (!((t - 1) & 3)) r = philox((uint32_t)((t - 1) >> 2), inst, ph, (uint32_t)TAG_POSMIN << 24, seed);
             const int q4 = (t - 1) & 3;
             const uint32_t u = q4 == 0 ? r.w[0] : (q4 == 1 ? r.w[1] : (q4 == 2 ? r.w[2] : r.w[3]));
-            const Sel s = pick_rth(dk, thr, u);
-            flip(s);
-            mark_tabu(s, t, tau);
+            const Sel s = ign ? pick_rth<true>(dk, u) : pick_rth<false>(dk, u);
+            flip_core(s);
+            refresh_all();
+            tabu_mark(s, t, tau, ign);
         }
-        ex_reset();
+        reset_marks();
         return T;
     }
 
@@ -638,7 +671,8 @@ struct Walker {
                 const int qmin = (8192 + n - 1) / n;
                 q = qq < qmin ? qmin : (qq > 256 ? 256 : qq);
             }
-            int kr = KEY_OUT;
+            tabu_release(t, tau);
+            uint32_t kr = UOUT;
             // lane's random words for slot s: wa (bytes of elements 0..3), wb (4..7)
             auto cand = [&](int s, uint32_t wa, uint32_t wb) {
 #pragma unroll
@@ -646,7 +680,7 @@ struct Walker {
                     const int j = s * V + e;
                     const uint32_t word = e < 4 ? wa : wb;
                     const int byte = (int)((word >> (8 * (e & 3))) & 0xFFu);
-                    kr = min(kr, (byte < q && ex[j] < t) ? K(j) : KEY_OUT);
+                    kr = min(kr, byte < q ? (uint32_t)kb[j] : UOUT);
                 }
             };
             const uint32_t tag = (uint32_t)TAG_RANDMIN << 24;
@@ -678,12 +712,23 @@ struct Walker {
                     cand(s, wa, wb);
                 }
             }
-            const int m = wave_min(kr >> LOGV);
-            const Sel s = empty_dom(m) ? dom_argmin(t) : argmin_from(kr, m);
-            flip(s);
-            mark_tabu(s, t, tau);
+            const int m = wave_min(wv(kr));
+            bool emp = false;
+            Sel s;
+            if (!none(m)) {
+                s = argmin_from(kr, m);
+            } else {
+                // no candidate: the non-tabu argmin, or the plain one when every bit is tabu
+                const uint32_t km = lane_umin();
+                const int mm = wave_min(wv(km));
+                emp = none(mm);
+                s = emp ? argmin_from(kminU, mU) : argmin_from(km, mm);
+            }
+            flip_core(s);
+            refresh_all();
+            tabu_mark(s, t, tau, emp);
         }
-        ex_reset();
+        reset_marks();
         return T;
     }
 

@@ -183,6 +183,16 @@ def test_problem_errors():
     with pytest.raises(dabs.DabsError) as ei:
         load(big)
     assert ei.value.status == dabs.DABS_E_RANGE
+    # int16 weights are negated in 16 bits by the search: -32768 off the
+    # diagonal is refused, on the diagonal (kept in 32 bits) accepted
+    m16 = np.zeros((8, 8), np.int16)
+    m16[2, 5] = m16[5, 2] = -32768
+    with pytest.raises(dabs.DabsError) as ei:
+        load(m16)
+    assert ei.value.status == dabs.DABS_E_RANGE
+    d16 = np.zeros((8, 8), np.int16)
+    d16[3, 3] = -32768
+    load(d16)
     too = np.zeros((dabs.dabs_max_n(dabs.DABS_W_I16) + 1,) * 2, np.int16)
     with pytest.raises(dabs.DabsError) as ei:
         load(too)
