@@ -10,9 +10,9 @@ template <typename WT, int SLOTS>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     const int wid = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     if (wid >= a.count) return;                       // whole wave leaves together
-    typedef typename Walker<WT, SLOTS>::vecE vecE;
-    vecE kb, mul;
-    Walker<WT, SLOTS> w(kb, mul);
+    typedef typename Walker<WT, SLOTS>::vecH vecH;
+    vecH kb0, kb1, mul0, mul1;
+    Walker<WT, SLOTS> w(kb0, kb1, mul0, mul1);
     w.setup((const WT *)a.W, a.diag, a.ld, a.n, a.seed, a.inst0 + (uint32_t)wid);
     uint64_t *x = a.x + (int64_t)wid * a.nwords;
     w.load_x(x);
@@ -60,14 +60,14 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 // a wave at 128 VGPRs; 1 leaves the whole register file to the allocator).
 template <typename WT, int SLOTS, int WPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_walk_items(ItemsArgs a) {
-    typedef typename Walker<WT, SLOTS>::vecE vecE;
-    vecE kb, mul;
+    typedef typename Walker<WT, SLOTS>::vecH vecH;
+    vecH kb0, kb1, mul0, mul1;
     const int lane = lane_id();
     const BatchDev &b = a.b;
     const int2 item = a.items[blockIdx.x];
     const int p = __builtin_amdgcn_readfirstlane(item.x), i = __builtin_amdgcn_readfirstlane(item.y);
     ProbDesc *d = b.desc + p;
-    Walker<WT, SLOTS> w(kb, mul);
+    Walker<WT, SLOTS> w(kb0, kb1, mul0, mul1);
     w.setup((const WT *)d->W, d->diag, d->ld, d->n, d->g.seed, (uint32_t)i);
     const int64_t gi = d->inst0 + i;
     const int64_t wo = d->inst_word0 + (int64_t)i * d->nw;

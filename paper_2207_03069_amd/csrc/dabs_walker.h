@@ -35,6 +35,52 @@ constexpr int KB_PAD = (int)0xFFFFFFF0u;
 // value the compiler turns select + min3 into a min followed by a select)
 constexpr uint32_t UOUT = 0xFFFFFFF0u;
 
+// N ints held in registers and indexed by a wave-uniform value without going
+// through memory: a uniform dynamic index becomes s_set_gpr_idx on a vector
+// of at most 32 registers (a larger vector would be indexed through scratch
+// memory, the whole vector stored and reloaded), so 64 elements are two
+// halves chosen by a uniform test.  The halves are the kernel's own local
+// vectors (which keeps them in registers); this refers to them.  Indices are
+// masked into range so that a speculated access of the other half stays
+// inside its vector.
+template <int N>
+struct RegVec {
+    static constexpr int H = N > 32 ? 32 : N;
+    typedef int vh __attribute__((ext_vector_type(H)));
+    vh &lo, &hi;    // hi is used only when N > 32
+    __device__ __forceinline__ RegVec(vh &l, vh &h) : lo(l), hi(h) {}
+    // (with a run-time index both halves are read and the value chosen, one
+    // half's value made opaque by an empty asm, and a store goes through one
+    // of two branches kept apart by an empty asm: a load or store through a
+    // pointer that selects between the halves would keep both in memory)
+    __device__ __forceinline__ int operator[](int j) const {
+        if constexpr (N <= 32) {
+            return lo[j];
+        } else {
+            if (__builtin_constant_p(j)) return j < H ? lo[j & (H - 1)] : hi[j & (H - 1)];
+            const int a = lo[j & (H - 1)];
+            int b = hi[j & (H - 1)];
+            asm volatile("" : "+v"(b));
+            return j < H ? a : b;
+        }
+    }
+    __device__ __forceinline__ void set(int j, int v) {
+        if constexpr (N <= 32) {
+            lo[j] = v;
+        } else if (__builtin_constant_p(j)) {
+            if (j < H) lo[j & (H - 1)] = v;
+            else hi[j & (H - 1)] = v;
+        } else {
+            if (j < H) {
+                lo[j & (H - 1)] = v;
+            } else {
+                hi[j & (H - 1)] = v;
+                asm volatile("");
+            }
+        }
+    }
+};
+
 struct Sel {
     int d;   // delta of the selected bit
     int i;   // global bit index
@@ -69,15 +115,11 @@ struct Walker {
     static constexpr int MUL0 = 1 << (KB + 1);
     static constexpr uint32_t MFLIP =
         sizeof(WT) == 2 ? ((0x10000u - (1u << (KB + 2))) & 0xFFFFu) : (uint32_t)(-(1 << (KB + 2)));
-    typedef int vecE __attribute__((ext_vector_type(EPL)));
+    typedef typename RegVec<EPL>::vh vecH;   // the kernel's local vectors (element j = s*V + e)
+    RegVec<EPL> kb, mul;
 
-    // The per-element vectors are the kernel's own local variables, one flat
-    // vector each (element j = s*V + e), which keeps them in registers and
-    // turns a uniform dynamic index into s_set_gpr_idx; the walker refers to
-    // them.
-    vecE &kb, &mul;
-
-    __device__ __forceinline__ Walker(vecE &kb_, vecE &mul_) : kb(kb_), mul(mul_) {}
+    __device__ __forceinline__ Walker(vecH &kb0, vecH &kb1, vecH &mul0, vecH &mul1)
+        : kb(kb0, kb1), mul(mul0, mul1) {}
 
     const WT *__restrict__ W;
     int64_t ld;
@@ -135,8 +177,8 @@ struct Walker {
                 const int j = s * V + e;
                 const int k = gidx(s, e);
                 if (k < n) vb |= 1ull << j;
-                kb[j] = k < n ? diag[k] * (1 << KB) + j + KBIAS : KB_PAD;   // X = 0: Delta_k = W_kk
-                mul[j] = (sizeof(WT) == 2 && (j & 1)) ? (int)((uint32_t)MUL0 << 16) : MUL0;
+                kb.set(j, k < n ? diag[k] * (1 << KB) + j + KBIAS : KB_PAD);   // X = 0: Delta_k = W_kk
+                mul.set(j, (sizeof(WT) == 2 && (j & 1)) ? (int)((uint32_t)MUL0 << 16) : MUL0);
             }
         xb = 0; bb = 0; E = 0; Eb = 0;
         ring = -1;
@@ -166,8 +208,8 @@ struct Walker {
                     // (element values first: a bit cast of a vector element
                     // expression would read the vector's first element)
                     const int m0 = mul[j], m1 = mul[j + 1];
-                    kb[j] = __builtin_amdgcn_sdot2(w2, __builtin_bit_cast(short2v, m0), kb[j], false);
-                    kb[j + 1] = __builtin_amdgcn_sdot2(w2, __builtin_bit_cast(short2v, m1), kb[j + 1], false);
+                    kb.set(j, __builtin_amdgcn_sdot2(w2, __builtin_bit_cast(short2v, m0), kb[j], false));
+                    kb.set(j + 1, __builtin_amdgcn_sdot2(w2, __builtin_bit_cast(short2v, m1), kb[j + 1], false));
                 }
             }
         } else {
@@ -177,7 +219,7 @@ struct Walker {
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
                     const int j = s * V + p;
-                    kb[j] = mad24(mad24((int)d[p], yi, 0), mul[j], kb[j]);
+                    kb.set(j, mad24(mad24((int)d[p], yi, 0), mul[j], kb[j]));
                 }
             }
         }
@@ -190,10 +232,10 @@ struct Walker {
         const bool xi = (readlane64(xb, s.L) >> s.j) & 1;
         update_row(s.i, xi ? -1 : 1);
         const int o = kb[s.j];
-        kb[s.j] = lane == s.L ? (2 * s.j + 2 * KBIAS) - o : o;
+        kb.set(s.j, lane == s.L ? (2 * s.j + 2 * KBIAS) - o : o);
         const int mo = mul[s.j];
         const uint32_t mf = (sizeof(WT) == 2 && (s.j & 1)) ? (MFLIP << 16) : MFLIP;
-        mul[s.j] = lane == s.L ? (int)((uint32_t)mo ^ mf) : mo;
+        mul.set(s.j, lane == s.L ? (int)((uint32_t)mo ^ mf) : mo);
         xb ^= lane == s.L ? (1ull << s.j) : 0ull;
     }
 
@@ -363,16 +405,16 @@ struct Walker {
     // ------------------------------------------------------------- exclusions
     __device__ __forceinline__ void mark(const Sel &s) {
         const int o = kb[s.j];
-        kb[s.j] = lane == s.L ? (int)((uint32_t)o | XBIT) : o;
+        kb.set(s.j, lane == s.L ? (int)((uint32_t)o | XBIT) : o);
     }
     __device__ __forceinline__ void unmark(int j, int L) {
         const int o = kb[j];
-        kb[j] = lane == L ? (o & 0x7FFFFFFF) : o;
+        kb.set(j, lane == L ? (o & 0x7FFFFFFF) : o);
     }
     // every valid bit back in the domain (padding stays out)
     __device__ __forceinline__ void reset_marks() {
 #pragma unroll
-        for (int j = 0; j < EPL; ++j) kb[j] = ((vb >> j) & 1) ? (kb[j] & 0x7FFFFFFF) : kb[j];
+        for (int j = 0; j < EPL; ++j) kb.set(j, ((vb >> j) & 1) ? (kb[j] & 0x7FFFFFFF) : kb[j]);
     }
 
     // Tabu (R11) of the bit flipped at iteration t.  maybe_marked: it was
@@ -428,7 +470,7 @@ struct Walker {
 #pragma unroll
         for (int j = 0; j < EPL; ++j) {
             const bool dif = (diff >> j) & 1;
-            kb[j] = dif ? (kb[j] & 0x7FFFFFFF) : (int)((uint32_t)kb[j] | XBIT);
+            kb.set(j, dif ? (kb[j] & 0x7FFFFFFF) : (int)((uint32_t)kb[j] | XBIT));
             hd += dif;
         }
         hd = (int)wave_sum64(hd);
