@@ -631,7 +631,10 @@ struct Walker {
         dom_minmax();                       // iteration 1: nothing is tabu
         FracStep fs;
         fs.init((uint32_t)T);
-        R4 r = {{0u, 0u, 0u, 0u}};
+        // iterations 2c+1 and 2c+2 use words (0, 1) and (2, 3) of draw c (R18);
+        // the draws are made 64 at a time, draw cbase + l in lane l
+        R4 rv = {{0u, 0u, 0u, 0u}};
+        int cbase = -64;
         for (int t = 1; t <= T; ++t) {
             fs.next();
             const bool ign = none(mM);      // every bit tabu: tabu ignored (R11)
@@ -644,9 +647,14 @@ struct Walker {
             }
             const int mind = dlt_w(mM);
             const int maxd = (mX - KBIAS) >> KB;
-            // iterations 2c+1 and 2c+2 use words (0, 1) and (2, 3) of draw c (R18)
-            if (!((t - 1) & 1)) r = philox((uint32_t)((t - 1) >> 1), inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
-            const uint32_t u = ((t - 1) & 1) ? r.w[2] : r.w[0], v = ((t - 1) & 1) ? r.w[3] : r.w[1];
+            const int c = (t - 1) >> 1;
+            if (c >= cbase + 64) {
+                cbase += 64;
+                rv = philox((uint32_t)(cbase + lane), inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
+            }
+            const bool second = (t - 1) & 1;
+            const uint32_t u = (uint32_t)readlane((int)(second ? rv.w[2] : rv.w[0]), c - cbase);
+            const uint32_t v = (uint32_t)readlane((int)(second ? rv.w[3] : rv.w[1]), c - cbase);
             const uint64_t g = fs.rest();   // floor(2^32 (T - t) / T)
             const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cube_frac(g)) >> 32;
             const int d = mind + (int)(((uint64_t)u * (span + 1)) >> 32);
@@ -669,7 +677,10 @@ struct Walker {
     __device__ __forceinline__ int phase_positivemin(int T, int tau, uint32_t ph) {
         constexpr uint32_t C = (uint32_t)KBIAS + (1u << KB);
         const bool may_empty = n <= tau;
-        R4 r = {{0u, 0u, 0u, 0u}};
+        // iterations 4c+1 .. 4c+4 use words 0 .. 3 of draw c (R18); the draws
+        // are made 64 at a time, draw cbase + l in lane l
+        R4 rv = {{0u, 0u, 0u, 0u}};
+        int cbase = -64;
         for (int t = 1; t <= T; ++t) {
             tabu_release(t, tau);
             bool ign = false;
@@ -685,10 +696,14 @@ struct Walker {
             const int mw = wave_min(wv(kp));
             const int d = none(mw) ? H_PAD - 1 : (mw >> SB) + 1;
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
-            // iterations 4c+1 .. 4c+4 use words 0 .. 3 of draw c (R18)
-            if (!((t - 1) & 3)) r = philox((uint32_t)((t - 1) >> 2), inst, ph, (uint32_t)TAG_POSMIN << 24, seed);
+            const int c = (t - 1) >> 2;
+            if (c >= cbase + 64) {
+                cbase += 64;
+                rv = philox((uint32_t)(cbase + lane), inst, ph, (uint32_t)TAG_POSMIN << 24, seed);
+            }
             const int q4 = (t - 1) & 3;
-            const uint32_t u = q4 == 0 ? r.w[0] : (q4 == 1 ? r.w[1] : (q4 == 2 ? r.w[2] : r.w[3]));
+            const uint32_t wq = q4 == 0 ? rv.w[0] : (q4 == 1 ? rv.w[1] : (q4 == 2 ? rv.w[2] : rv.w[3]));
+            const uint32_t u = (uint32_t)readlane((int)wq, c - cbase);
             const Sel s = ign ? pick_rth<true>(dk, u) : pick_rth<false>(dk, u);
             flip_core(s);
             refresh_all();
