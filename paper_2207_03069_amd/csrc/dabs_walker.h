@@ -594,28 +594,22 @@ struct Walker {
         Sel out;
         out.L = 0; out.j = 0; out.i = 0;
         at_slot(slot, [&](int ss) {
-            uint64_t cm[V];
-            int cnt = 0;
-            uint32_t excl = 0;
+            // excl: candidates of the slot in lower lanes; cb: this lane's own
+            uint32_t excl = 0, cb = 0;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                cm[e] = ballot(cand(ss * V + e));
-                cnt += __builtin_amdgcn_inverse_ballot_w64(cm[e]) ? 1 : 0;
-                excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm[e] >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)cm[e], excl));
+                const uint64_t cm = ballot(cand(ss * V + e));
+                cb |= __builtin_amdgcn_inverse_ballot_w64(cm) ? (1u << e) : 0u;
+                excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, excl));
             }
-            const uint64_t own = ballot(excl <= rr && rr < excl + (uint32_t)cnt);
-            const int L = own ? (int)__builtin_ctzll(own) : 0;
-            int left = (int)(rr - (uint32_t)readlane((int)excl, L));
-            int e_sel = 0;
-            bool got = false;
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                if (!got && ((cm[e] >> L) & 1)) {
-                    if (left == 0) { e_sel = e; got = true; }
-                    else left--;
-                }
-            }
+            // excl does not decrease with the lane, so the lanes with excl <= rr
+            // are a prefix (lane 0 at least) whose last lane holds candidate rr
+            const uint64_t le = ballot(excl <= rr);
+            const int L = 63 - __builtin_clzll(le | 1ull);
+            const int left = (int)(rr - (uint32_t)readlane((int)excl, L));
+            uint32_t b = (uint32_t)readlane((int)cb, L);
+            for (int k = 0; k < left && k < V; ++k) b &= b - 1;   // drop the lane's first `left` candidates
+            const int e_sel = b ? (int)__builtin_ctz(b) : 0;
             out.L = L;
             out.j = ss * V + e_sel;
             out.i = ss * SPAN + L * V + e_sel;
