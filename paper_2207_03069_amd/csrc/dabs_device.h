@@ -7,15 +7,12 @@
 // vectors: V = 16 / sizeof(weight) elements per lane per slot, SLOTS slots
 // cover n.  Lane l holds, for slot s and sub-index e < V, bit
 // k = s*64*V + l*V + e at local index j = s*V + e.  Per element the lane keeps
-//   h[j]  the local field  W_kk + 2 sum_{m != k} W_km x_m  (so that
-//         Delta_k = (1 - 2 x_k) h_k, Section III-A Eq. (3) in the full-sum
-//         convention), updated on a flip of bit i by h_k += 2 (1 - 2 x_i) W_ik
-//         (Eq. (4); the device copy of W has a zero diagonal, so h_i itself is
-//         unchanged, which is Eq. (5) once x_i flips);
-//   s2[j] (1 - 2 x_k) * 2^KB, so that key_j = h_j * s2_j + j = Delta_k 2^KB + j
-//         is one 24-bit multiply-add and orders by (Delta, k) within the lane;
-//   ex[j] the first iteration from which element j is back in the rule's
-//         domain (tabu, Straight's differing bits, padding).
+// one word kb[j] = Delta_k 2^KB + j + 2^29 (+ 2^31 while bit k is outside the
+// rule's domain), with Delta_k = (1 - 2 x_k)(W_kk + 2 sum_{m != k} W_km x_m)
+// (Section III-A Eq. (3) in the full-sum convention), updated on a flip of
+// bit i by Delta_k += 2 (1 - 2 x_i)(1 - 2 x_k) W_ik (Eq. (4); the device copy
+// of W has a zero diagonal) and Delta_i -> -Delta_i (Eq. (5)); and one
+// multiplier word mul[j] = (1 - 2 x_k) 2^(KB+1) for that update.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,13 +20,9 @@
 namespace dabs {
 
 constexpr int WAVE = 64;
-constexpr int H_PAD = (1 << 23) - 1;     // local field of padding elements
-constexpr int KEY_BIG = 0x7fffffff;
-// Key of an element outside a rule's domain in masked minima.  Above every
-// real key (padding included: H_PAD << 6 < 2^29) but below INT_MAX, so that
-// min(m, in ? k : KEY_OUT) stays a select followed by a 3-input minimum (with
-// INT_MAX the compiler rewrites it as in ? min(m, k) : m, one more VALU op).
-constexpr int KEY_OUT = 0x7ffffff0;
+// above every delta (|Delta| <= B < 2^23 - 1): PositiveMin's threshold when no
+// delta of the domain is positive
+constexpr int H_PAD = (1 << 23) - 1;
 constexpr int TAU_MAX = 16;
 constexpr int64_t E_INF = INT64_MAX;
 
