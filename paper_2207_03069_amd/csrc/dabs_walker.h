@@ -558,6 +558,25 @@ struct Walker {
         return T;
     }
 
+    // Position of set bit number k (0-based, k < popcount(b)) of a V-bit mask,
+    // by halving with popcounts: no data-dependent loop.
+    static __device__ __forceinline__ int kth_bit(uint32_t b, uint32_t k) {
+        int base = 0;
+        if constexpr (V == 8) {
+            const uint32_t c = (uint32_t)__builtin_popcount(b & 0xFu);
+            const bool up = k >= c;
+            k -= up ? c : 0u;
+            b >>= up ? 4 : 0;
+            base += up ? 4 : 0;
+        }
+        const uint32_t c2 = (uint32_t)__builtin_popcount(b & 0x3u);
+        const bool up2 = k >= c2;
+        k -= up2 ? c2 : 0u;
+        b >>= up2 ? 2 : 0;
+        base += up2 ? 2 : 0;
+        return base + (k >= (b & 1u) ? 1 : 0);
+    }
+
     // Candidates: unexcluded elements (IGN: exclusions ignored, padding still
     // out) whose key is <= dk.  Counts them, draws r = floor(v * count / 2^32)
     // and returns the r-th candidate (0-based, in increasing bit index: slot,
@@ -598,8 +617,12 @@ struct Walker {
             uint32_t excl = 0, cb = 0;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                const uint64_t cm = ballot(cand(ss * V + e));
-                cb |= __builtin_amdgcn_inverse_ballot_w64(cm) ? (1u << e) : 0u;
+                // the same test as cand(), written apart so that it is made
+                // here as a lane mask rather than carried over from the counts
+                const uint32_t kj = IGN ? ((uint32_t)kb[ss * V + e] & 0x7FFFFFFFu) : (uint32_t)kb[ss * V + e];
+                const bool ce = kj < lim + 1u;
+                const uint64_t cm = ballot(ce);
+                cb |= ce ? (1u << e) : 0u;
                 excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, excl));
             }
             // excl does not decrease with the lane, so the lanes with excl <= rr
@@ -607,9 +630,8 @@ struct Walker {
             const uint64_t le = ballot(excl <= rr);
             const int L = 63 - __builtin_clzll(le | 1ull);
             const int left = (int)(rr - (uint32_t)readlane((int)excl, L));
-            uint32_t b = (uint32_t)readlane((int)cb, L);
-            for (int k = 0; k < left && k < V; ++k) b &= b - 1;   // drop the lane's first `left` candidates
-            const int e_sel = b ? (int)__builtin_ctz(b) : 0;
+            // (uniform by construction; said so, the element index stays scalar)
+            const int e_sel = __builtin_amdgcn_readfirstlane(kth_bit((uint32_t)readlane((int)cb, L), (uint32_t)left));
             out.L = L;
             out.j = ss * V + e_sel;
             out.i = ss * SPAN + L * V + e_sel;
