@@ -186,16 +186,18 @@ struct Walker {
         trace = nullptr; trace_cap = 0; flips = 0;
     }
 
-    // kb_k += 2 y_i y_k W_ik 2^KB for all k (row i of the zero-diagonal copy
-    // of W, y = 1 - 2x).  The padded rows hold zeros, so every lane loads
-    // every slot.  int16: y_i W is one packed 16-bit multiply per word (the
-    // library rejects -32768 in int16 W, so the negation is exact).
-    __device__ __forceinline__ void update_row(int i, int yi) {
+    // Row i of the zero-diagonal copy of W as this lane's 16-byte pieces.  The
+    // padded rows hold zeros, so every lane loads every slot.
+    __device__ __forceinline__ void load_row(int i, uint4 (&q)[SLOTS]) const {
         if ((unsigned)i >= (unsigned)n) i = 0;     // never read outside W (a selection bug shows in parity)
         const WT *row = W + (int64_t)i * ld + lane * V;
-        uint4 q[SLOTS];
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) q[s] = *(const uint4 *)(row + s * SPAN);
+    }
+    // kb_k += 2 y_i y_k W_ik 2^KB for all k (y = 1 - 2x) from the loaded row.
+    // int16: y_i W is one packed 16-bit multiply per word (the library rejects
+    // -32768 in int16 W, so the negation is exact).
+    __device__ __forceinline__ void apply_row(const uint4 (&q)[SLOTS], int yi) {
         if constexpr (sizeof(WT) == 2) {
             const short2v y2 = {(short)yi, (short)yi};
 #pragma unroll
@@ -228,9 +230,15 @@ struct Walker {
     // Flip the (uniform) selected bit: every word by Eq. (4), the bit's own
     // word by Eq. (5) (its key k becomes 2j - k; the exclusion bit is kept
     // because 2 * 2^31 vanishes mod 2^32), its multiplier negated.
-    __device__ __forceinline__ void flip_bit(const Sel &s) {
+    // `during` is work independent of the search state, done while the row
+    // load is in flight.
+    template <class F>
+    __device__ __forceinline__ void flip_bit(const Sel &s, F &&during) {
+        uint4 q[SLOTS];
+        load_row(s.i, q);
         const bool xi = (readlane64(xb, s.L) >> s.j) & 1;
-        update_row(s.i, xi ? -1 : 1);
+        during();
+        apply_row(q, xi ? -1 : 1);
         const int o = kb[s.j];
         kb.set(s.j, lane == s.L ? (2 * s.j + 2 * KBIAS) - o : o);
         const int mo = mul[s.j];
@@ -259,7 +267,7 @@ struct Walker {
                 word &= word - 1;
                 const Sel s = uniform(sel_of(w * 64 + b));
                 E += s.d;
-                flip_bit(s);
+                flip_bit(s, [] {});
             }
         }
     }
@@ -390,13 +398,15 @@ struct Walker {
     }
 
     // Step 3: flip the selected bit, update E and every word.
-    __device__ __forceinline__ void flip_core(const Sel &s0) {
+    template <class F>
+    __device__ __forceinline__ void flip_core(const Sel &s0, F &&during) {
         const Sel s = uniform(s0);
         E += s.d;
-        flip_bit(s);
+        flip_bit(s, during);
         if (trace && flips < trace_cap && lane == 0) trace[flips] = s.i;
         flips++;
     }
+    __device__ __forceinline__ void flip_core(const Sel &s0) { flip_core(s0, [] {}); }
     __device__ __forceinline__ void flip(const Sel &s) {
         flip_core(s);
         refresh();
@@ -651,8 +661,25 @@ struct Walker {
         // the draws are made 64 at a time, draw cbase + l in lane l
         R4 rv = {{0u, 0u, 0u, 0u}};
         int cbase = -64;
-        for (int t = 1; t <= T; ++t) {
+        // the random words u, v and the cube fraction of iteration t depend on
+        // t only: they are made for iteration t + 1 while the row of iteration
+        // t loads
+        uint32_t u, v;
+        uint64_t cf;
+        auto prepare = [&](int t) {
             fs.next();
+            cf = cube_frac(fs.rest());      // fs.rest() = floor(2^32 (T - t) / T)
+            const int c = (t - 1) >> 1;
+            if (c >= cbase + 64) {
+                cbase += 64;
+                rv = philox((uint32_t)(cbase + lane), inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
+            }
+            const bool second = (t - 1) & 1;
+            u = (uint32_t)readlane((int)(second ? rv.w[2] : rv.w[0]), c - cbase);
+            v = (uint32_t)readlane((int)(second ? rv.w[3] : rv.w[1]), c - cbase);
+        };
+        prepare(1);
+        for (int t = 1; t <= T; ++t) {
             const bool ign = none(mM);      // every bit tabu: tabu ignored (R11)
             if (ign) {
                 mM = mU;
@@ -663,21 +690,12 @@ struct Walker {
             }
             const int mind = dlt_w(mM);
             const int maxd = (mX - KBIAS) >> KB;
-            const int c = (t - 1) >> 1;
-            if (c >= cbase + 64) {
-                cbase += 64;
-                rv = philox((uint32_t)(cbase + lane), inst, ph, (uint32_t)TAG_MAXMIN << 24, seed);
-            }
-            const bool second = (t - 1) & 1;
-            const uint32_t u = (uint32_t)readlane((int)(second ? rv.w[2] : rv.w[0]), c - cbase);
-            const uint32_t v = (uint32_t)readlane((int)(second ? rv.w[3] : rv.w[1]), c - cbase);
-            const uint64_t g = fs.rest();   // floor(2^32 (T - t) / T)
-            const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cube_frac(g)) >> 32;
+            const uint64_t span = ((uint64_t)(uint32_t)(maxd - mind) * cf) >> 32;
             const int d = mind + (int)(((uint64_t)u * (span + 1)) >> 32);
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
             const Sel s = ign ? pick_rth<true>(dk, v) : pick_rth<false>(dk, v);
             tabu_mark(s, t, tau, ign);
-            flip_core(s);
+            flip_core(s, [&] { if (t < T) prepare(t + 1); });
             tabu_release(t + 1, tau);
             dom_minmax();
             step1();
@@ -733,6 +751,26 @@ struct Walker {
     __device__ __forceinline__ int phase_randommin(int T, int tau, uint32_t ph) {
         FracStep fs;
         fs.init((uint32_t)T);
+        // Lanes 2m and 2m+1 share the draw of bits 16m .. 16m+15 of a slot
+        // (bytes 0..7 and 8..15) when V = 8 and the slots pair up: even lanes
+        // draw for even slots, odd lanes for odd slots, and each pair swaps
+        // the halves.  Otherwise each lane draws per slot.
+        constexpr bool PAIRS = V == 8 && SLOTS % 2 == 0;
+        constexpr int ND = PAIRS ? SLOTS / 2 : SLOTS;
+        // with few draws per lane, iteration t + 1's draws are made while the
+        // row of iteration t loads (they depend on t only)
+        constexpr bool AHEAD = ND <= 2;
+        const uint32_t tag = (uint32_t)TAG_RANDMIN << 24;
+        const bool odd = lane & 1;
+        auto draw = [&](int t, int k) -> R4 {
+            const int s_own = PAIRS ? 2 * k + (odd ? 1 : 0) : k;
+            return philox((uint32_t)t, inst, ph, tag | (uint32_t)((s_own * SPAN + lane * V) >> 4), seed);
+        };
+        R4 rd[ND];
+        if constexpr (AHEAD) {
+#pragma unroll
+            for (int k = 0; k < ND; ++k) rd[k] = draw(1, k);
+        }
         for (int t = 1; t <= T; ++t) {
             fs.next();
             int q;
@@ -756,33 +794,26 @@ struct Walker {
                     kr = min(kr, byte < q ? (uint32_t)kb[j] : UOUT);
                 }
             };
-            const uint32_t tag = (uint32_t)TAG_RANDMIN << 24;
-            if constexpr (V == 8 && SLOTS % 2 == 0) {
-                // Lanes 2m and 2m+1 share the draw of bits 16m .. 16m+15 of a
-                // slot (bytes 0..7 and 8..15).  Even lanes draw for even slots,
-                // odd lanes for odd slots, and each pair swaps the halves.
-                const bool odd = lane & 1;
 #pragma unroll
-                for (int u = 0; u < SLOTS; u += 2) {
-                    const int s_own = u + (odd ? 1 : 0);
-                    const R4 r = philox((uint32_t)t, inst, ph, tag | (uint32_t)((s_own * SPAN + lane * V) >> 4), seed);
+            for (int k = 0; k < ND; ++k) {
+                R4 r;
+                if constexpr (AHEAD) r = rd[k];
+                else r = draw(t, k);
+                if constexpr (PAIRS) {
+                    const int u = 2 * k;
                     const uint32_t ra = swap_pair(odd ? r.w[0] : r.w[2]);
                     const uint32_t rb = swap_pair(odd ? r.w[1] : r.w[3]);
                     // slot u: even lane own words 0, 1; odd lane the even neighbour's 2, 3
                     cand(u, odd ? ra : r.w[0], odd ? rb : r.w[1]);
                     // slot u+1: even lane the odd neighbour's 0, 1; odd lane own 2, 3
                     cand(u + 1, odd ? r.w[2] : ra, odd ? r.w[3] : rb);
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    const int k0 = s * SPAN + lane * V;
-                    const R4 r = philox((uint32_t)t, inst, ph, tag | (uint32_t)(k0 >> 4), seed);
+                } else {
                     // this lane's V bytes start at byte (k0 mod 16) of the draw
+                    const int k0 = k * SPAN + lane * V;
                     const int w0 = (k0 & 15) >> 2;
                     const uint32_t wa = w0 == 0 ? r.w[0] : (w0 == 1 ? r.w[1] : (w0 == 2 ? r.w[2] : r.w[3]));
                     const uint32_t wb = w0 == 0 ? r.w[1] : (w0 == 1 ? r.w[2] : r.w[3]);
-                    cand(s, wa, wb);
+                    cand(k, wa, wb);
                 }
             }
             const int m = wave_min(wv(kr));
@@ -797,7 +828,14 @@ struct Walker {
                 emp = none(mm);
                 s = emp ? argmin_from(kminU, mU) : argmin_from(km, mm);
             }
-            flip_core(s);
+            flip_core(s, [&] {
+                if constexpr (AHEAD) {
+                    if (t < T) {
+#pragma unroll
+                        for (int k = 0; k < ND; ++k) rd[k] = draw(t + 1, k);
+                    }
+                }
+            });
             refresh_all();
             tabu_mark(s, t, tau, emp);
         }
