@@ -127,6 +127,21 @@ def test_search_parity_maxcut_and_small_tau(n, wt):
         compare(gpu_search(p, rule, X0, **kw), oracle_search(W, rule, X0, **kw), 300)
 
 
+@pytest.mark.parametrize("n,wt,tau", [(5, np.int16, 8), (8, np.int32, 16), (16, np.int16, 16), (300, np.int16, 8),
+                                      (3000, np.int16, 8)])
+def test_search_parity_long_phases(n, wt, tau):
+    """Phases longer than one batch of the lane-parallel draws (MaxMin: 128
+    iterations, PositiveMin: 256), domains that empty (n <= tau: tabu bits
+    selected again), and the two-half register vectors of int16 n > 2048."""
+    W = inputs.dense_qubo(n, -300, 300, 77 + n, dtype=wt)
+    p = load(W)
+    X0 = inputs.random_bits(3, n, 11 * n)
+    cap = 700
+    for rule in (oracle.MAXMIN, oracle.POSITIVEMIN, oracle.RANDOMMIN, oracle.CYCLICMIN, oracle.TABU_GREEDY):
+        kw = dict(T=600, tau=tau, seed=4242, phase=1, inst0=3, trace_cap=cap)
+        compare(gpu_search(p, rule, X0, **kw), oracle_search(W, rule, X0, **kw), cap)
+
+
 def test_c1_full_size():
     """24-bit workload at its full size: 64 tabu-greedy instances (tau = 4) of
     2000 flips from seeded X0; bit-exact, and the best equals the certified
