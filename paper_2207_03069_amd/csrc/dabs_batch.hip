@@ -181,6 +181,49 @@ __global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
 // than the worst entry and no identical vector is pooled; ascending energies,
 // a newcomer after equal energies.  The energy / algorithm / operation
 // columns are worked on in LDS; each lane moves only its own words.
+// Cost rank of a search rule (measured per flip: MaxMin, PositiveMin,
+// RandomMin, CyclicMin, tabu greedy, TwoNeighbor, then the rest).
+__device__ __forceinline__ int rule_rank(int a) {
+    switch (a) {
+    case MAXMIN: return 0;
+    case POSITIVEMIN: return 1;
+    case RANDOMMIN: return 2;
+    case CYCLICMIN: return 3;
+    case TABU_GREEDY: return 4;
+    case TWONEIGHBOR: return 5;
+    default: return 6;
+    }
+}
+
+// The items of each problem reordered by the cost of the rule its instance
+// runs this round, costliest first.  Workgroups are handed to the compute
+// units in index order, so each cost class spreads over all SIMDs instead of
+// piling up wherever the random choice of rules put it.  Only the launch
+// order changes: every item still runs once, and items are independent.
+// One workgroup per problem; item0[p] is the problem's first item.
+__global__ __launch_bounds__(256) void k_sort_items(BatchDev b, int2 *items, const int *item0) {
+    const int p = blockIdx.x;
+    const ProbDesc &d = b.desc[p];
+    __shared__ int cnt[8];
+    if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.instances; i += blockDim.x) atomicAdd(&cnt[rule_rank(b.algo[d.inst0 + i])], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int r = 0; r < 8; ++r) {
+            const int c = cnt[r];
+            cnt[r] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.instances; i += blockDim.x) {
+        const int pos = atomicAdd(&cnt[rule_rank(b.algo[d.inst0 + i])], 1);
+        items[item0[p] + pos] = make_int2(p, i);
+    }
+}
+
 __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pools) {
     __shared__ long long se[POOL_MAX];
     __shared__ int sal[POOL_MAX], sop[POOL_MAX];
@@ -288,6 +331,7 @@ struct dabs_batched {
     int64_t total_inst, pool_cells, pool_words, inst_words;
     BatchDev d;
     int2 *items;                       // device, grouped by class
+    int *item0;                        // device, first item of each problem
     int2 *pool_list;                   // device, (problem, pool)
     int npool_list;
     struct Cls { int wtype, slots, begin, count, variant; };
@@ -324,7 +368,7 @@ static void batched_free(dabs_batched *s) {
         if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
     void *ptrs[] = {s->d.desc, s->d.pool_bits, s->d.pool_e, s->d.pool_algo, s->d.pool_op, s->d.x, s->d.target,
                     s->d.best, s->d.e, s->d.best_e, s->d.ph, s->d.algo, s->d.op, s->d.inst_prob, s->d.ctr,
-                    s->items, s->pool_list};
+                    s->items, s->item0, s->pool_list};
     for (void *q : ptrs) (void)hipFree(q);
     (void)hipFree(s->mlp_cnt);
     (void)hipFree(s->mlp_feat);
@@ -381,6 +425,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
     s->total_inst = inst; s->pool_cells = cells; s->pool_words = pwords; s->inst_words = iwords;
     // items grouped by (wtype, slots), longest first inside a class
     std::vector<int2> items;
+    std::vector<int> item0(nprob);
     std::vector<std::pair<int, int>> keys;
     for (int p = 0; p < nprob; ++p) keys.push_back({s->hdesc[p].wtype, s->hdesc[p].slots});
     std::sort(keys.begin(), keys.end());
@@ -399,8 +444,10 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         });
         // default variant until tuned: measured faster uncapped from 4 slots up
         dabs_batched::Cls c = {k.first, k.second, (int)items.size(), 0, k.second >= 4 ? 1 : 0};
-        for (int p : ps)
+        for (int p : ps) {
+            item0[p] = (int)items.size();
             for (int i = 0; i < s->hdesc[p].instances; ++i) items.push_back(make_int2(p, i));
+        }
         c.count = (int)items.size() - c.begin;
         s->classes.push_back(c);
     }
@@ -424,6 +471,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
               hipMalloc(&d.inst_prob, 4 * (size_t)inst) == hipSuccess &&
               hipMalloc(&d.ctr, 8 * 3) == hipSuccess &&
               hipMalloc(&s->items, sizeof(int2) * items.size()) == hipSuccess &&
+              hipMalloc(&s->item0, sizeof(int) * nprob) == hipSuccess &&
               hipMalloc(&s->pool_list, sizeof(int2) * pl.size()) == hipSuccess;
     if (!ok) {
         batched_free(s);
@@ -443,6 +491,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
     // instances start at X = 0 with E = 0 (Section III-B)
     ok = hipMemcpyAsync(d.desc, s->hdesc.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st) == hipSuccess &&
          hipMemcpyAsync(s->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(s->item0, item0.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st) == hipSuccess &&
          hipMemcpyAsync(s->pool_list, pl.data(), sizeof(int2) * pl.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
          hipMemcpyAsync(d.inst_prob, ip.data(), 4 * ip.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
          hipMemsetAsync(d.x, 0, 8 * (size_t)iwords, st) == hipSuccess &&
@@ -476,6 +525,8 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
         }
     hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
                        (int)s->total_inst);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_items, dim3((unsigned)s->nprob), dim3(256), 0, st, s->d, s->items, s->item0);
     HIP_OK(hipGetLastError());
     const bool timed = s->timed && !capturing;
     if (timed && s->nev == dabs_batched::NEV) {
@@ -668,6 +719,7 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
     if (status == DABS_OK) {
         hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
                            (int)s->total_inst);
+        hipLaunchKernelGGL(k_sort_items, dim3((unsigned)s->nprob), dim3(256), 0, st, s->d, s->items, s->item0);
         if (hipGetLastError() != hipSuccess) status = dabs_fail(DABS_E_HIP, "target generation failed");
     }
     for (size_t c = 0; c < s->classes.size() && status == DABS_OK; ++c) {
