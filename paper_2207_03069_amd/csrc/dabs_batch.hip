@@ -176,11 +176,6 @@ __global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
     }
 }
 
-// Packet insertion (Section III-C, IV): one wave per (problem, pool), the
-// pool's instances in increasing order; insert only when strictly better
-// than the worst entry and no identical vector is pooled; ascending energies,
-// a newcomer after equal energies.  The energy / algorithm / operation
-// columns are worked on in LDS; each lane moves only its own words.
 // Cost rank of a search rule (measured per flip: MaxMin, PositiveMin,
 // RandomMin, CyclicMin, tabu greedy, TwoNeighbor, then the rest).
 __device__ __forceinline__ int rule_rank(int a) {
@@ -224,6 +219,11 @@ __global__ __launch_bounds__(256) void k_sort_items(BatchDev b, int2 *items, con
     }
 }
 
+// Packet insertion (Section III-C, IV): one wave per (problem, pool), the
+// pool's instances in increasing order; insert only when strictly better
+// than the worst entry and no identical vector is pooled; ascending energies,
+// a newcomer after equal energies.  The energy / algorithm / operation
+// columns are worked on in LDS; each lane moves only its own words.
 __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pools) {
     __shared__ long long se[POOL_MAX];
     __shared__ int sal[POOL_MAX], sop[POOL_MAX];

@@ -50,12 +50,14 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 }
 
 // One wavefront (one 64-thread workgroup) per (problem, instance) item.  The
-// items of a size class are sorted longest first and the hardware dispatcher
-// hands out workgroups in index order as waves retire, which balances the
-// uneven items without a software queue.  Items are deliberately not popped
-// from an atomic counter inside a loop: with a lane-0 epilogue in the same
-// loop, the compiler may split it into nested loops so that lanes 1..63
-// re-enter the pop without lane 0 (and read item 0 again, forever).
+// problems of a size class are ordered longest first, and inside a problem the
+// items are reordered every round by the cost of the rule they run, costliest
+// first; the hardware dispatcher hands out workgroups in index order as waves
+// retire, which balances the uneven items without a software queue.  Items
+// are deliberately not popped from an atomic counter inside a loop: with a
+// lane-0 epilogue in the same loop, the compiler may split it into nested
+// loops so that lanes 1..63 re-enter the pop without lane 0 (and read item 0
+// again, forever).
 // WPE: the minimum waves per SIMD the register allocation must allow (4 caps
 // a wave at 128 VGPRs; 1 leaves the whole register file to the allocator).
 template <typename WT, int SLOTS, int WPE>
