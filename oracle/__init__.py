@@ -21,7 +21,9 @@ _SRC = os.path.join(_HERE, "dabs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 GREEDY, STRAIGHT, MAXMIN, CYCLICMIN, RANDOMMIN, POSITIVEMIN, TWONEIGHBOR, TABU_GREEDY = range(8)
-OP_RANDOM, OP_BEST, OP_MUTATION, OP_CROSSOVER, OP_XROSSOVER, OP_ZERO, OP_ONE, OP_INTERVALZERO = range(8)
+(OP_RANDOM, OP_BEST, OP_MUTATION, OP_CROSSOVER, OP_XROSSOVER, OP_ZERO, OP_ONE, OP_INTERVALZERO,
+ OP_MLP_SEED, OP_MLP_MUTATE) = range(10)
+GA_RESTART = 2                      # flag: restart the pools when they have merged
 MAIN_ALGOS = (MAXMIN, CYCLICMIN, RANDOMMIN, POSITIVEMIN, TWONEIGHBOR)
 ALL_OPS = tuple(range(8))
 P_EXPLORE_5PCT = 214748365          # ceil(0.05 * 2^32)
@@ -35,7 +37,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-                               "-o", tmp, _SRC])
+                               "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -48,12 +50,12 @@ class GAParams(C.Structure):
                 ("crossover_kind", C.c_int32), ("capacity", C.c_int32),
                 ("npools", C.c_int32), ("tau", C.c_int32),
                 ("T", C.c_int64), ("Bn", C.c_int64), ("greedy_cap", C.c_int64),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("flags", C.c_uint32), ("merge_hamming", C.c_int32)]
 
 
 def ga_params(*, T, Bn, tau=8, seed=0, capacity=100, npools=1, algos=MAIN_ALGOS, ops=ALL_OPS,
               p_explore=P_EXPLORE_5PCT, p_mutation=P_EIGHTH, p_zero=P_EIGHTH, p_one=P_EIGHTH,
-              crossover_kind=0, greedy_cap=GREEDY_CAP_DEFAULT) -> GAParams:
+              crossover_kind=0, greedy_cap=GREEDY_CAP_DEFAULT, flags=0, merge_hamming=0) -> GAParams:
     g = GAParams()
     g.n_algos = len(algos)
     for i, a in enumerate(algos):
@@ -64,7 +66,11 @@ def ga_params(*, T, Bn, tau=8, seed=0, capacity=100, npools=1, algos=MAIN_ALGOS,
     g.p_explore, g.p_mutation, g.p_zero, g.p_one = p_explore, p_mutation, p_zero, p_one
     g.crossover_kind, g.capacity, g.npools, g.tau = crossover_kind, capacity, npools, tau
     g.T, g.Bn, g.greedy_cap, g.seed = T, Bn, greedy_cap, seed
+    g.flags, g.merge_hamming = flags, merge_hamming
     return g
+
+
+SCORE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.POINTER(C.c_uint8), C.POINTER(C.c_float))
 
 
 _lib = None
@@ -97,6 +103,12 @@ def lib():
         L.orc_batch_search.restype = i64
         L.orc_solve.argtypes = [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, i32]
         L.orc_solve.restype = i64
+        L.orc_solve_ex.argtypes = [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, i32,
+                                   SCORE_FN, P, P, P, P]
+        L.orc_solve_ex.restype = i64
+        L.orc_target_from_pools.argtypes = [i32, P, P, P, P, P, P, u32, u32, P, P, P]
+        L.orc_randmin_q.argtypes = [i64, i64, i32]
+        L.orc_randmin_q.restype = i32
         L.orc_first_target.argtypes = [i32, P, u32, P, P, P]
         L.orc_first_target.restype = i32
         L.orc_all_energies.argtypes = [P, i32, P]
@@ -206,11 +218,22 @@ def batch_search(W, rule, x0, target, *, T, Bn, tau=0, seed=0, inst=0, ph=0,
                 trace=trace[:min(f, trace_cap)] if trace_cap else None)
 
 
-def solve(W, g: GAParams, instances: int, rounds: int, verify=False):
-    """Generational DABS loop; returns pools, per-instance state and insert log."""
+def solve(W, g: GAParams, instances: int, rounds: int, verify=False, score=None):
+    """Generational DABS loop; returns pools, per-instance state, insert log,
+    the best pooled vector over the run (kept across restarts) and the number
+    of restarts.  score(round, pool_bits [P][m][n] uint8) -> float32 logits
+    [P][m][n] gives the learned scores of every pooled bit at the start of a
+    round (the MLP operations copy their parent without it)."""
     W = _w(W)
     n = W.shape[0]
     P, m = g.npools, g.capacity
+    cb = SCORE_FN()
+    if score is not None:
+        def _cb(ctx, rnd, bits, out):
+            pb = np.ctypeslib.as_array(bits, shape=(P, m, n)).copy()
+            z = np.ascontiguousarray(np.asarray(score(int(rnd), pb), dtype=np.float32).reshape(P * m * n))
+            np.ctypeslib.as_array(out, shape=(P * m * n,))[:] = z
+        cb = SCORE_FN(_cb)
     pb = np.zeros((P, m, n), dtype=np.uint8)
     pe = np.zeros((P, m), dtype=np.int64)
     pa = np.zeros((P, m), dtype=np.int32)
@@ -221,12 +244,40 @@ def solve(W, g: GAParams, instances: int, rounds: int, verify=False):
     ins = np.zeros((max(rounds, 1), instances), dtype=np.int32)
     tg = np.zeros((instances, n), dtype=np.uint8)
     pk = np.zeros(instances, dtype=np.int64)
-    f = lib().orc_solve(_p(W), n, C.byref(g), instances, rounds, _p(pb), _p(pe), _p(pa), _p(po),
-                        _p(x), _p(e), _p(ph), _p(ins), _p(tg), _p(pk), int(verify))
+    bb = np.zeros(n, dtype=np.uint8)
+    be = C.c_int64()
+    nr = C.c_int32()
+    f = lib().orc_solve_ex(_p(W), n, C.byref(g), instances, rounds, _p(pb), _p(pe), _p(pa), _p(po),
+                           _p(x), _p(e), _p(ph), _p(ins), _p(tg), _p(pk), int(verify), cb, None,
+                           _p(bb), C.byref(be), C.byref(nr))
     if f < 0:
         raise RuntimeError("oracle solve failed (%d)" % f)
     return dict(flips=int(f), pool_bits=pb, pool_e=pe, pool_algo=pa, pool_op=po, x=x, e=e, ph=ph,
-                inserts=ins[:rounds], targets=tg, packets=pk)
+                inserts=ins[:rounds], targets=tg, packets=pk, best_bits=bb, best_e=int(be.value),
+                restarts=int(nr.value))
+
+
+def target_from_pools(g: GAParams, pool_bits, inst, rnd=0, pool_e=None, pool_algo=None, pool_op=None,
+                      logits=None):
+    """The target (and algorithm, operation) that instance `inst` draws in
+    round `rnd` from the given pools ([P][m][n] 0/1)."""
+    pb = np.ascontiguousarray(np.asarray(pool_bits, dtype=np.uint8))
+    P, m, n = pb.shape
+    assert (P, m) == (g.npools, g.capacity)
+    pe = np.ascontiguousarray(pool_e if pool_e is not None else np.zeros((P, m)), dtype=np.int64)
+    pa = np.ascontiguousarray(pool_algo if pool_algo is not None else np.full((P, m), MAXMIN), dtype=np.int32)
+    po = np.ascontiguousarray(pool_op if pool_op is not None else np.zeros((P, m)), dtype=np.int32)
+    lg = None if logits is None else np.ascontiguousarray(np.asarray(logits, dtype=np.float32).reshape(P, m, n))
+    t = np.zeros(n, dtype=np.uint8)
+    a, o = C.c_int32(), C.c_int32()
+    lib().orc_target_from_pools(n, C.byref(g), _p(pb), _p(pe), _p(pa), _p(po), _p(lg), rnd, inst, _p(t),
+                                C.byref(a), C.byref(o))
+    return t, int(a.value), int(o.value)
+
+
+def randmin_q(t: int, T: int, n: int) -> int:
+    """RandomMin's candidate threshold at iteration t (in 1/256 units)."""
+    return int(lib().orc_randmin_q(t, T, n))
 
 
 def first_target(n, g: GAParams, inst):

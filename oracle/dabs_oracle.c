@@ -21,15 +21,21 @@
  *
  * Pins: energies, deltas, Greedy, Straight, TwoNeighbor, tabu-greedy,
  * CyclicMin, Step 1, the batch schedule, rank selection, the genetic
- * operations and the pools are pinned by the tests against scratch energies,
- * brute force, printed examples and closed forms.  The random choices of
- * MaxMin, PositiveMin and RandomMin (which candidate a draw selects) are
- * parity unpinned: tests pin only their properties (threshold ranges,
- * candidate sets, the argmin at t = T); the exact choice is fixed by the
- * readings R6, R7, R9 and R18 and by agreement with the device.
+ * operations (IntervalZero's single cyclic segment and its length range
+ * included), the learned operations (equivalences with Mutation at
+ * hand-derived thresholds), the restart of merged pools and the pools are
+ * pinned by the tests against scratch energies, brute force, printed
+ * examples and closed forms.  The random choices of MaxMin, PositiveMin and
+ * RandomMin are pinned in distribution: RandomMin's candidate rate against
+ * the real schedule max((t/T)^3, 32/n), the MaxMin / PositiveMin pick by
+ * chi-square uniformity over fixed candidate sets, plus their threshold
+ * ranges and candidate sets.  Which candidate one particular draw selects
+ * (the readings R6, R7, R9 and R18) is fixed only by agreement with the
+ * device.
  */
 #include <stdint.h>
 #include <stdlib.h>
+#include <math.h>
 #include <string.h>
 #include "dabs_oracle.h"
 
@@ -281,6 +287,11 @@ static int32_t randmin_q(int64_t t, int64_t T, int32_t n)
     if (q < qmin) q = qmin;
     if (q > 256) q = 256;
     return (int32_t)q;
+}
+
+int32_t orc_randmin_q(int64_t t, int64_t T, int32_t n)
+{
+    return randmin_q(t, T, n);
 }
 
 /* R7: MaxMin threshold d drawn uniformly from [minD, D(t)] with
@@ -629,17 +640,18 @@ static int rand_vec_bit(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag, int
 }
 
 /* Section IV-A: initial pools hold random vectors with energy +inf and random
- * algorithm / operation columns (R17). */
-static void pools_init(pools_t *p, const orc_ga_params *g)
+ * algorithm / operation columns (R17).  Epoch e > 0 is the refill after the
+ * e-th restart (Section IV-B, R24): its own draws, sub-tags 2e and 2e + 1. */
+static void pools_init(pools_t *p, const orc_ga_params *g, uint32_t epoch)
 {
     for (int32_t q = 0; q < p->npools; q++)
         for (int32_t r = 0; r < p->cap; r++) {
             uint8_t *b = entry_bits(p, q, r);
             for (int32_t k = 0; k < p->n; k++)
                 b[k] = (uint8_t)rand_vec_bit(g->seed, (uint32_t)r, (uint32_t)q,
-                                             ((uint32_t)TAG_POOL << 24) | 1u, k);
+                                             ((uint32_t)TAG_POOL << 24) | (2u * epoch + 1u), k);
             uint32_t w[4];
-            draw4(g->seed, (uint32_t)r, (uint32_t)q, 0, (uint32_t)TAG_POOL << 24, w);
+            draw4(g->seed, (uint32_t)r, (uint32_t)q, 0, ((uint32_t)TAG_POOL << 24) | (2u * epoch), w);
             p->e[(int64_t)q * p->cap + r] = INT64_MAX;
             p->algo[(int64_t)q * p->cap + r] = g->algos[scale_u32(w[0], (uint32_t)g->n_algos)];
             p->op[(int64_t)q * p->cap + r] = g->ops[scale_u32(w[1], (uint32_t)g->n_ops)];
@@ -663,9 +675,35 @@ static uint32_t ga_bit_u32(uint64_t seed, uint32_t round, uint32_t inst, int32_t
     return r[k % 4];
 }
 
-/* Target generation for one instance (Section IV-A, IV-B; R17). */
+/* The learned operations (R22; not in the paper) on parent a with logits z
+ * (one float32 per bit, the network's scores of that pooled vector):
+ *   MLP-seed flips every bit whose logit is positive;
+ *   MLP-mutate flips bit k when its per-bit u32 draw is below 2^29 + q_k 2^22,
+ *   q_k = clamp(round-half-even(16 z_k), -128, 127): the Mutation rate 1/8
+ *   tilted by the logit. */
+static void mlp_operation(int32_t op, const uint8_t *a, const float *z, int32_t n, uint64_t seed,
+                          uint32_t round, uint32_t inst, uint8_t *target)
+{
+    for (int32_t k = 0; k < n; k++) {
+        int flip;
+        if (op == ORC_OP_MLP_SEED) {
+            flip = z[k] > 0.0f;
+        } else {
+            float lv = nearbyintf(16.0f * z[k]);      /* default rounding: half to even */
+            if (lv < -128.0f) lv = -128.0f;
+            if (lv > 127.0f) lv = 127.0f;
+            int64_t thr = ((int64_t)1 << 29) + (int64_t)lv * ((int64_t)1 << 22);
+            flip = (int64_t)ga_bit_u32(seed, round, inst, k) < thr;
+        }
+        target[k] = a[k] ^ (uint8_t)flip;
+    }
+}
+
+/* Target generation for one instance (Section IV-A, IV-B; R17).  logits
+ * (nullable, [npools][cap][n]) are the learned scores of every pooled bit;
+ * without them the learned operations copy their parent. */
 static void ga_target(const pools_t *p, const orc_ga_params *g, uint32_t round, uint32_t inst,
-                      uint8_t *target, int32_t *algo_out, int32_t *op_out)
+                      uint8_t *target, int32_t *algo_out, int32_t *op_out, const float *logits)
 {
     const int32_t n = p->n, m = p->cap;
     const int32_t q = (int32_t)(inst % (uint32_t)p->npools);
@@ -682,7 +720,8 @@ static void ga_target(const pools_t *p, const orc_ga_params *g, uint32_t round, 
     *op_out = op;
     *algo_out = algo;
 
-    const uint8_t *a = entry_bits(p, q, (int32_t)orc_rank_index(v[0], (uint32_t)m));
+    const int32_t ra = (int32_t)orc_rank_index(v[0], (uint32_t)m);
+    const uint8_t *a = entry_bits(p, q, ra);
     const int32_t qn = (q + 1) % p->npools;
     const uint8_t *b = entry_bits(p, op == ORC_OP_XROSSOVER ? qn : q,
                                   (int32_t)orc_rank_index(v[1], (uint32_t)m));
@@ -732,6 +771,13 @@ static void ga_target(const pools_t *p, const orc_ga_params *g, uint32_t round, 
         for (uint32_t o = 0; o < len; o++) target[(s + o) % (uint32_t)n] = 0;
         break;
     }
+    case ORC_OP_MLP_SEED:
+    case ORC_OP_MLP_MUTATE:
+        if (logits)
+            mlp_operation(op, a, logits + ((int64_t)q * m + ra) * n, n, g->seed, round, inst, target);
+        else
+            memcpy(target, a, (size_t)n);
+        break;
     default:
         memcpy(target, a, (size_t)n);
         break;
@@ -763,22 +809,52 @@ static int32_t pool_insert(pools_t *p, int32_t q, const uint8_t *bits, int64_t e
     return pos;
 }
 
+/* Restart on merge (Section IV-B, R24): the pools have merged when every
+ * entry has been evaluated and lies within Hamming distance h of the best
+ * pooled vector (the rank-0 entry of lowest energy, lowest pool on ties). */
+static int pools_merged(const pools_t *p, int32_t h)
+{
+    int32_t qb = 0;
+    for (int32_t q = 1; q < p->npools; q++)
+        if (p->e[(int64_t)q * p->cap] < p->e[(int64_t)qb * p->cap]) qb = q;
+    const uint8_t *best = entry_bits(p, qb, 0);
+    for (int32_t q = 0; q < p->npools; q++)
+        for (int32_t r = 0; r < p->cap; r++) {
+            if (p->e[(int64_t)q * p->cap + r] == INT64_MAX) return 0;
+            const uint8_t *b = entry_bits(p, q, r);
+            int32_t d = 0;
+            for (int32_t k = 0; k < p->n; k++) d += b[k] != best[k];
+            if (d > h) return 0;
+        }
+    return 1;
+}
+
 /* Generational DABS loop on one problem.  Instances start at X = 0 (Section
  * III-B) and keep X across rounds.  Outputs the pools and per-instance final
  * X, E and main-phase counters; inserts[] (optional, [rounds][instances])
  * records each packet's insert position (-1 if rejected); targets_out
  * (optional, [instances][n]) the last round's targets; packets_out (optional,
- * [instances]) the last round's packet energies.  Returns total flips or a
- * negative code. */
-int64_t orc_solve(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t instances,
-                  int32_t rounds, uint8_t *pool_bits, int64_t *pool_e, int32_t *pool_algo,
-                  int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
-                  int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify)
+ * [instances]) the last round's packet energies.
+ *
+ * score (nullable) is called at the start of every round with the pools as
+ * they stand and fills logits[npools][cap][n], the learned scores the
+ * MLP-seed / MLP-mutate operations use (R22).  With ORC_GA_RESTART set in
+ * g->flags the pools restart when merged (R24); best_bits / best_e (nullable)
+ * receive the best pooled vector seen over all rounds and epochs and
+ * restarts_out the number of restarts.  Returns total flips or a negative
+ * code. */
+int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t instances,
+                     int32_t rounds, uint8_t *pool_bits, int64_t *pool_e, int32_t *pool_algo,
+                     int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
+                     int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify,
+                     orc_score_fn score, void *score_ctx, uint8_t *best_bits, int64_t *best_e,
+                     int32_t *restarts_out)
 {
     if (n < 1 || instances < 1 || g->npools < 1 || g->capacity < 1) return -1;
     if (g->n_algos < 1 || g->n_ops < 1) return -1;
     pools_t p = {n, g->capacity, g->npools, pool_bits, pool_e, pool_algo, pool_op};
-    pools_init(&p, g);
+    uint32_t epoch = 0;
+    pools_init(&p, g, epoch);
     uint8_t *x = (uint8_t *)calloc((size_t)instances * n, 1);
     uint8_t *tg = (uint8_t *)malloc((size_t)instances * n);
     uint8_t *bb = (uint8_t *)malloc((size_t)instances * n);
@@ -787,11 +863,16 @@ int64_t orc_solve(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t i
     int32_t *op = (int32_t *)malloc(sizeof(int32_t) * (size_t)instances);
     uint32_t *ph = (uint32_t *)calloc((size_t)instances, sizeof(uint32_t));
     int64_t *delta = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    float *logits = score ? (float *)malloc(sizeof(float) * (size_t)g->npools * g->capacity * n) : NULL;
+    uint8_t *record = (uint8_t *)malloc((size_t)n);
+    int64_t record_e = INT64_MAX;
+    memset(record, 0, (size_t)n);
     int64_t total = 0;
     int err = 0;
     for (int32_t r = 0; r < rounds && !err; r++) {
+        if (score) score(score_ctx, r, p.bits, logits);
         for (int32_t i = 0; i < instances; i++)
-            ga_target(&p, g, (uint32_t)r, (uint32_t)i, tg + (int64_t)i * n, &al[i], &op[i]);
+            ga_target(&p, g, (uint32_t)r, (uint32_t)i, tg + (int64_t)i * n, &al[i], &op[i], logits);
         for (int32_t i = 0; i < instances; i++) {
             state_t st;
             state_load(&st, W, n, x + (int64_t)i * n, delta, bb + (int64_t)i * n);
@@ -808,12 +889,47 @@ int64_t orc_solve(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t i
             if (inserts) inserts[(int64_t)r * instances + i] = pos;
         }
         if (packets_out) memcpy(packets_out, eb, sizeof(int64_t) * (size_t)instances);
+        /* the run's best pooled vector so far (kept across restarts) */
+        for (int32_t q = 0; q < g->npools; q++)
+            if (p.e[(int64_t)q * p.cap] < record_e) {
+                record_e = p.e[(int64_t)q * p.cap];
+                memcpy(record, entry_bits(&p, q, 0), (size_t)n);
+            }
+        if ((g->flags & ORC_GA_RESTART) && pools_merged(&p, g->merge_hamming)) {
+            epoch++;
+            pools_init(&p, g, epoch);
+        }
     }
     if (x_out) memcpy(x_out, x, (size_t)instances * n);
     if (targets_out) memcpy(targets_out, tg, (size_t)instances * n);
     if (ph_out) memcpy(ph_out, ph, sizeof(uint32_t) * (size_t)instances);
-    free(x); free(tg); free(bb); free(eb); free(al); free(op); free(ph); free(delta);
+    if (best_bits) memcpy(best_bits, record, (size_t)n);
+    if (best_e) *best_e = record_e;
+    if (restarts_out) *restarts_out = (int32_t)epoch;
+    free(x); free(tg); free(bb); free(eb); free(al); free(op); free(ph); free(delta); free(logits);
+    free(record);
     return err ? -2 : total;
+}
+
+int64_t orc_solve(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t instances,
+                  int32_t rounds, uint8_t *pool_bits, int64_t *pool_e, int32_t *pool_algo,
+                  int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
+                  int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify)
+{
+    return orc_solve_ex(W, n, g, instances, rounds, pool_bits, pool_e, pool_algo, pool_op, x_out,
+                        e_out, ph_out, inserts, targets_out, packets_out, verify, NULL, NULL, NULL,
+                        NULL, NULL);
+}
+
+/* One target drawn by ga_target from pools the caller supplies (bits
+ * [npools][cap][n], energies, columns; logits nullable as in orc_solve_ex),
+ * for pinning the genetic operations on chosen parents. */
+void orc_target_from_pools(int32_t n, const orc_ga_params *g, uint8_t *pool_bits, int64_t *pool_e,
+                           int32_t *pool_algo, int32_t *pool_op, const float *logits, uint32_t round,
+                           uint32_t inst, uint8_t *target, int32_t *algo, int32_t *op)
+{
+    pools_t p = {n, g->capacity, g->npools, pool_bits, pool_e, pool_algo, pool_op};
+    ga_target(&p, g, round, inst, target, algo, op, logits);
 }
 
 /* One round-0 target as orc_solve would draw it from freshly initialised
@@ -825,8 +941,8 @@ int32_t orc_first_target(int32_t n, const orc_ga_params *g, uint32_t inst, uint8
     pools_t p = {n, g->capacity, g->npools,
                  (uint8_t *)malloc((size_t)(cells * n)), (int64_t *)malloc(sizeof(int64_t) * (size_t)cells),
                  (int32_t *)malloc(sizeof(int32_t) * (size_t)cells), (int32_t *)malloc(sizeof(int32_t) * (size_t)cells)};
-    pools_init(&p, g);
-    ga_target(&p, g, 0, inst, target, algo, op);
+    pools_init(&p, g, 0);
+    ga_target(&p, g, 0, inst, target, algo, op, NULL);
     free(p.bits); free(p.e); free(p.algo); free(p.op);
     return 0;
 }

@@ -19,8 +19,12 @@ enum {
 /* Genetic operations (Section IV-A, IV-B). */
 enum {
     ORC_OP_RANDOM = 0, ORC_OP_BEST = 1, ORC_OP_MUTATION = 2, ORC_OP_CROSSOVER = 3,
-    ORC_OP_XROSSOVER = 4, ORC_OP_ZERO = 5, ORC_OP_ONE = 6, ORC_OP_INTERVALZERO = 7
+    ORC_OP_XROSSOVER = 4, ORC_OP_ZERO = 5, ORC_OP_ONE = 6, ORC_OP_INTERVALZERO = 7,
+    ORC_OP_MLP_SEED = 8, ORC_OP_MLP_MUTATE = 9   /* learned operations (R22) */
 };
+
+/* flags of orc_ga_params */
+enum { ORC_GA_RESTART = 2 };   /* restart the pools when they have merged (R24) */
 
 typedef struct {
     int32_t n_algos;
@@ -39,7 +43,13 @@ typedef struct {
     int64_t Bn;              /* batch flips (b n) */
     int64_t greedy_cap;      /* bound on one Greedy phase */
     uint64_t seed;           /* key of the counter-based generator */
+    uint32_t flags;          /* ORC_GA_RESTART */
+    int32_t merge_hamming;   /* restart: merged when every entry is within this distance of the best */
 } orc_ga_params;
+
+/* Scores of every pooled bit at the start of round `round`:
+ * pool_bits [npools][cap][n] -> logits [npools][cap][n]. */
+typedef void (*orc_score_fn)(void *ctx, int32_t round, const uint8_t *pool_bits, float *logits);
 
 void orc_philox(const uint32_t ctr[4], uint64_t seed, uint32_t out[4]);
 int64_t orc_energy(const int32_t *W, int32_t n, const uint8_t *x);
@@ -64,6 +74,19 @@ int64_t orc_solve(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t i
                   int32_t rounds, uint8_t *pool_bits, int64_t *pool_e, int32_t *pool_algo,
                   int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
                   int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify);
+
+int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t instances,
+                     int32_t rounds, uint8_t *pool_bits, int64_t *pool_e, int32_t *pool_algo,
+                     int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
+                     int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify,
+                     orc_score_fn score, void *score_ctx, uint8_t *best_bits, int64_t *best_e,
+                     int32_t *restarts_out);
+
+void orc_target_from_pools(int32_t n, const orc_ga_params *g, uint8_t *pool_bits, int64_t *pool_e,
+                           int32_t *pool_algo, int32_t *pool_op, const float *logits, uint32_t round,
+                           uint32_t inst, uint8_t *target, int32_t *algo, int32_t *op);
+
+int32_t orc_randmin_q(int64_t t, int64_t T, int32_t n);
 
 int32_t orc_first_target(int32_t n, const orc_ga_params *g, uint32_t inst, uint8_t *target,
                          int32_t *algo, int32_t *op);

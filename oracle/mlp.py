@@ -231,3 +231,17 @@ def mlp_mutate(parent, logits, seed, rnd, inst):
         if ga_bit_u32(seed, rnd, inst, k) < (1 << 29) + q[k] * (1 << 22):
             out[k] ^= 1
     return out
+
+
+def pool_logits(params, W, pool_bits):
+    """Logits of every bit of every pooled vector ([P][m][n] 0/1 ->
+    float32 [P][m][n]): the features of entry r of pool q (rank r within
+    pool q) through the network, as a round with a network attached scores
+    its pools before target generation."""
+    pool_bits = np.asarray(pool_bits, dtype=np.uint8)
+    P, m, n = pool_bits.shape
+    out = np.zeros((P, m, n), dtype=np.float32)
+    for q in range(P):
+        for r in range(m):
+            out[q, r] = forward(params, features(W, pool_bits[q, r], pool_bits[q], r)).astype(np.float32)
+    return out
