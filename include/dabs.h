@@ -335,6 +335,24 @@ int dabs_mlp_params(const dabs_mlp *m, float *params_dev, void *stream);
  * the stream. */
 int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev, int32_t npools, int32_t capacity,
                            uint16_t *feat_dev, void *stream);
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * features as dabs_mlp_pool_features, bit for bit, with no allocation and no
+ * synchronisation (asynchronous on `stream`).  The per-pool bit counts
+ * ([npools][n] int) that the other call allocates per call live here in a
+ * static device buffer of DABS_NOALLOC_COUNTS ints (1 MiB) that the library
+ * keeps on each GPU it runs on until the process ends; its address is looked
+ * up on the first call on a device.  Every count is rewritten before it is
+ * read, so nothing carries over between calls, but calls that overlap on one
+ * GPU (two streams, or two threads) share the buffer and race: serialise them.
+ * The current device must be the problem's.
+ * Errors: DABS_E_INVALID (null, bad shape, npools * n > DABS_NOALLOC_COUNTS,
+ * another device current), DABS_E_UNSUPPORTED (n > 4096), DABS_E_HIP.
+ */
+#define DABS_NOALLOC_COUNTS 262144
+int dabs_mlp_pool_features_noalloc(const dabs_problem *p, const uint64_t *pool_bits_dev, int32_t npools,
+                                   int32_t capacity, uint16_t *feat_dev, void *stream);
 /* labels_dev[e][k] = bit k of bits_dev[e] != bit k of ref_dev (u8, count x n).
  * symmetric != 0: against ref or its complement, whichever is nearer in
  * Hamming distance (ties: ref) -- for problems whose energy is invariant under

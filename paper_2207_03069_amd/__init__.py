@@ -22,6 +22,7 @@ DABS_W_I16, DABS_W_I32 = 0, 1
 (DABS_OP_RANDOM, DABS_OP_BEST, DABS_OP_MUTATION, DABS_OP_CROSSOVER, DABS_OP_XROSSOVER, DABS_OP_ZERO,
  DABS_OP_ONE, DABS_OP_INTERVALZERO, DABS_OP_MLP_SEED, DABS_OP_MLP_MUTATE) = range(10)
 DABS_MLP_PARAMS = 4801
+DABS_NOALLOC_COUNTS = 262144
 MAIN_ALGOS = (DABS_MAXMIN, DABS_CYCLICMIN, DABS_RANDOMMIN, DABS_POSITIVEMIN, DABS_TWONEIGHBOR)
 
 
@@ -85,6 +86,7 @@ _SIGS = {
     "dabs_mlp_destroy": ([_P], C.c_int),
     "dabs_mlp_params": ([_P, _P, _P], C.c_int),
     "dabs_mlp_pool_features": ([_P, _P, C.c_int32, C.c_int32, _P, _P], C.c_int),
+    "dabs_mlp_pool_features_noalloc": ([_P, _P, C.c_int32, C.c_int32, _P, _P], C.c_int),
     "dabs_mlp_labels": ([_P, _P, C.c_int64, _P, C.c_int32, _P, _P], C.c_int),
     "dabs_mlp_forward": ([_P, C.c_int64, _P, _P, _P], C.c_int),
     "dabs_mlp_grad": ([_P, C.c_int64, _P, _P, _P, _P, _P], C.c_int),
@@ -360,6 +362,11 @@ def dabs_mlp_params(m: Mlp, out, stream=None):
 
 def dabs_mlp_pool_features(p: Problem, pool_bits, npools: int, capacity: int, feat, stream=None):
     _check(lib().dabs_mlp_pool_features(p.handle, _ptr(pool_bits), npools, capacity, _ptr(feat), _stream(stream)))
+
+
+def dabs_mlp_pool_features_noalloc(p: Problem, pool_bits, npools: int, capacity: int, feat, stream=None):
+    _check(lib().dabs_mlp_pool_features_noalloc(p.handle, _ptr(pool_bits), npools, capacity, _ptr(feat),
+                                                _stream(stream)))
 
 
 def dabs_mlp_labels(p: Problem, bits, count: int, ref, labels, symmetric: bool = False, stream=None):

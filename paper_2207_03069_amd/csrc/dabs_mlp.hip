@@ -18,6 +18,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "dabs_device.h"
 #include "dabs_internal.h"
 
@@ -515,6 +517,62 @@ int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev,
         r = dabs_fail(DABS_E_HIP, "feature kernels failed");
     (void)hipFree(cnt);
     return r;
+}
+
+}  // extern "C"
+
+namespace dabs {
+// Per-pool bit counts of dabs_mlp_pool_features_noalloc: one copy per GPU,
+// held until the process ends.  Host code never passes this name to a kernel
+// (on the host it is a stand-in, not a device address): it uses the address
+// that hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) int scratch[DABS_NOALLOC_COUNTS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static int *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.
+static int scratch_on_current_device(int **out) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return dabs_fail(DABS_E_UNSUPPORTED, "device %d above the %d devices the no-allocation call serves", dev,
+                         NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return dabs_fail(DABS_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (int *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DABS_OK;
+}
+}  // namespace dabs
+
+extern "C" {
+
+int dabs_mlp_pool_features_noalloc(const dabs_problem *p, const uint64_t *pool_bits_dev, int32_t npools,
+                                   int32_t capacity, uint16_t *feat_dev, void *stream) {
+    if (!p || !pool_bits_dev || !feat_dev) return dabs_fail(DABS_E_INVALID, "null argument");
+    if (npools < 1 || capacity < 1) return dabs_fail(DABS_E_INVALID, "bad pool shape");
+    if (p->n > 4096) return dabs_fail(DABS_E_UNSUPPORTED, "features need n <= 4096");
+    if ((int64_t)npools * p->n > DABS_NOALLOC_COUNTS)
+        return dabs_fail(DABS_E_INVALID, "npools * n = %lld above the %d counts of the static buffer",
+                         (long long)npools * p->n, DABS_NOALLOC_COUNTS);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != p->device)
+        return dabs_fail(DABS_E_INVALID, "current device %d is not the problem's device %d", dev, p->device);
+    int *cnt = nullptr;
+    const int r = scratch_on_current_device(&cnt);
+    if (r != DABS_OK) return r;
+    // every count is written by k_pool_counts before k_features reads it, so
+    // nothing has to be cleared between calls
+    return mlp_pool_logits(p, nullptr, pool_bits_dev, npools, capacity, cnt, (short *)feat_dev, nullptr,
+                           (hipStream_t)stream);
 }
 
 int dabs_mlp_labels(const dabs_problem *p, const uint64_t *bits_dev, int64_t count, const uint64_t *ref_dev,
