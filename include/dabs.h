@@ -42,7 +42,8 @@ typedef enum {
     DABS_E_RANGE = -3,          /* W too large for the exact device representation */
     DABS_E_NOMEM = -4,          /* device allocation failed */
     DABS_E_HIP = -5,            /* a HIP runtime call failed */
-    DABS_E_UNSUPPORTED = -6     /* n outside the sizes this build supports */
+    DABS_E_UNSUPPORTED = -6,    /* n outside the sizes this build supports */
+    DABS_E_CANCELLED = -7       /* the caller's cancel flag is set (see dabs_solver_set_cancel) */
 } dabs_status;
 
 typedef enum { DABS_W_I16 = 0, DABS_W_I32 = 1 } dabs_wtype;
@@ -74,20 +75,28 @@ const char *dabs_strerror(int status);
 const char *dabs_last_error(void);
 /* Largest n this build supports for a weight type. */
 int32_t dabs_max_n(int32_t wtype);
+/* Largest delta bound B (see dabs_problem_create) the search accepts for n
+ * bits of a weight type: 2^(29 - K) - 2 with K = max(log2 V, ceil(log2(V s)))
+ * (V = 8 int16 / 4 int32 elements per 16-byte piece, s the power-of-two
+ * count of 64 V-bit slots that covers n); -1 for an unsupported n or type. */
+int64_t dabs_max_bound(int32_t wtype, int32_t n);
 
 /*
  * Load a QUBO matrix (the W of Section II, Eq. (2)).
  *   w_dev  device pointer to an n x n row-major matrix of int16 (wtype
  *          DABS_W_I16) or int32 (DABS_W_I32) with row stride ld >= n elements.
  * The library validates W on the device (symmetry; delta bound
- * B = max_k |W_kk| + 2 sum_{j!=k} |W_kj| < 2^23 - 1, which keeps every delta and
- * local field exact in the device representation; int16 weights off the
- * diagonal in [-32767, 32767], since the search negates them in 16 bits),
- * then copies it into its own padded layout.  This call synchronises `stream` once (validation
+ * B = max_k |W_kk| + 2 sum_{j!=k} |W_kj| <= dabs_max_bound(wtype, n), which
+ * keeps every delta and local field exact in the device representation:
+ * 2^23 - 2 at n = 4096 int16, up to 2^27 - 2 at n <= 256 int32; int16
+ * weights off the diagonal in [-32767, 32767], since the search negates them
+ * in 16 bits; int32 weights off the diagonal in [-(2^23 - 1), 2^23 - 1], the
+ * operand range of the 24-bit multiply of the update), then copies it into
+ * its own padded layout.  This call synchronises `stream` once (validation
  * result); the caller may free w_dev afterwards.
  * Errors: DABS_E_INVALID (null, n < 1, ld < n, bad wtype), DABS_E_UNSUPPORTED
- * (n > dabs_max_n), DABS_E_NOT_SYMMETRIC, DABS_E_RANGE (B >= 2^23 - 1, or an
- * int16 -32768 off the diagonal),
+ * (n > dabs_max_n), DABS_E_NOT_SYMMETRIC, DABS_E_RANGE (B above
+ * dabs_max_bound, or an off-diagonal weight outside the ranges above),
  * DABS_E_NOMEM, DABS_E_HIP.  *out is set only on success.
  */
 int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
@@ -182,11 +191,23 @@ typedef struct {
     int32_t T;
     int32_t Bn;
     int32_t greedy_cap;
-    uint32_t flags;          /* DABS_SOLVER_TIME_WALK: time every batch-search launch with HIP events */
+    uint32_t flags;          /* DABS_SOLVER_TIME_WALK, DABS_GA_RESTART */
+    int32_t merge_hamming;   /* DABS_GA_RESTART: merged when every entry is within this distance of the best */
     uint64_t seed;
 } dabs_ga_params;
 
+/* time every batch-search launch with HIP events (dabs_solver_timing) */
 #define DABS_SOLVER_TIME_WALK 1u
+/* Restart of merged pools (Section IV-B): after the packets of a round are
+ * inserted, the pools count as merged when every entry has been evaluated
+ * (finite energy) and lies within Hamming distance merge_hamming of the best
+ * pooled vector (the rank-0 entry of least energy, lowest pool on ties); they
+ * are then refilled with fresh random vectors of energy +inf and random
+ * algorithm / operation columns (the draws of refill e use Philox sub-tags
+ * 2e + 1 for the bits and 2e for the columns of TAG_POOL; the first fill is
+ * e = 0).  Instances keep their X.  The best vector of the run survives in
+ * the record (dabs_solver_record). */
+#define DABS_GA_RESTART 2u
 
 /*
  * Solver: `instances` search instances and `npools` solution pools on one
@@ -236,6 +257,33 @@ int dabs_solver_state(const dabs_solver *s, uint64_t *x_dev, int64_t *e_dev, uin
 int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream);
 
 /*
+ * The run's record: the best pooled vector seen at the end of any round so
+ * far (kept across restarts), bits_dev [nwords] (nullable), and out_dev int64
+ * [3] = (its energy (INT64_MAX before the first round), restarts so far,
+ * rounds completed; cancelled rounds are not counted).
+ */
+int dabs_solver_record(const dabs_solver *s, uint64_t *bits_dev, int64_t *out_dev, void *stream);
+
+/*
+ * Cancellation (Section III-B: the device repeats batch searches until the
+ * host requests termination).  flag_host is a 32-bit word of pinned host
+ * memory that the device can read (hipHostMalloc, or a tensor created with
+ * pin_memory=True); NULL detaches.  While *flag_host != 0:
+ *   - dabs_solver_run returns DABS_E_CANCELLED at once and enqueues nothing;
+ *   - a round already enqueued that starts its searches while the flag is
+ *     set does nothing: no batch search runs, the pools, instances, record
+ *     and round counter stay as they were (so a run resumed after the flag is
+ *     cleared continues exactly as if the cancelled rounds had not been
+ *     enqueued).  The flag is read once per round, before its searches
+ *     start, so a round in progress finishes.
+ * Every kernel still runs to its normal end.  The memory must stay valid
+ * until it is detached or the solver is destroyed.
+ * Errors: DABS_E_INVALID (null solver, or flag_host not pinned host memory
+ * visible to the device).
+ */
+int dabs_solver_set_cancel(dabs_solver *s, const volatile int32_t *flag_host);
+
+/*
  * Batch-search kernel timing of a solver created with DABS_SOLVER_TIME_WALK:
  * out_host[0] = summed elapsed milliseconds of the batch-search launches,
  * out_host[1] = number of launches, out_host[2] = flips they made (all since
@@ -280,6 +328,11 @@ int dabs_batched_state(const dabs_batched *b, int32_t prob, uint64_t *x_dev, int
 int dabs_batched_flips(const dabs_batched *b, int64_t *total_flips_dev, void *stream);
 /* As dabs_solver_timing (DABS_SOLVER_TIME_WALK in any problem's flags). */
 int dabs_batched_timing(dabs_batched *b, double *out_host, int32_t reset);
+/* As dabs_solver_record for problem `prob` (the round counter is the batch's). */
+int dabs_batched_record(const dabs_batched *b, int32_t prob, uint64_t *bits_dev, int64_t *out_dev, void *stream);
+/* As dabs_solver_set_cancel, for every problem of the batch (graph replays
+ * included: the flag is read by the device). */
+int dabs_batched_set_cancel(dabs_batched *b, const volatile int32_t *flag_host);
 
 /*
  * Autotuner: for every size class of the batch (weight type x slot count),
@@ -295,6 +348,24 @@ int dabs_batched_timing(dabs_batched *b, double *out_host, int32_t reset);
 int dabs_batched_autotune(dabs_batched *b, double *ms_out, int32_t *choice_out, void *stream);
 int dabs_solver_autotune(dabs_solver *s, double *ms_out, int32_t *choice_out, void *stream);
 int dabs_batched_classes(const dabs_batched *b, int32_t *wtype_slots_count_variant, int32_t cap);
+
+/*
+ * Ising front-end (Section I, Eq. (1)): H(S) = sum_{(i,j) in E} J_ij s_i s_j
+ * + sum_i h_i s_i over spins s_i in {-1, +1}.  With s_i = 2 x_i - 1 the
+ * equivalent QUBO (Eq. (2), full ordered sum) has W_ij = W_ji = 2 J_ij
+ * (i != j) and W_ii = 2 h_i - 2 sum_{j ~ i} J_ij, and E(X) = H(S) + c with
+ * c = sum_i h_i - sum_E J_ij.
+ *   edges_dev [nedges][2] int32 node pairs (i != j, both < n), J_dev [nedges]
+ *   int32 interactions (an edge listed twice adds), h_dev [n] int32 biases;
+ *   W_dev: n x n int32 output, row stride ld >= n (its first n columns are
+ *   overwritten: the call clears them first); offset_dev: int64 [2] = (c,
+ *   number of edges skipped because i == j or an index is out of range).
+ * Asynchronous on `stream`; the result is exact as long as every W entry fits
+ * int32 (|2 h_i| + 2 sum_j |J_ij| < 2^31); load W with dabs_problem_create.
+ * Errors: DABS_E_INVALID (null, n < 1, ld < n, nedges < 0).
+ */
+int dabs_ising_to_qubo(int32_t n, int64_t nedges, const int32_t *edges_dev, const int32_t *J_dev,
+                       const int32_t *h_dev, int32_t *W_dev, int64_t ld, int64_t *offset_dev, void *stream);
 
 /*
  * Learned proposal.  Not in the paper: a small network that scores every bit

@@ -170,6 +170,44 @@ def is_symmetric(W) -> bool:
     return bool(lib().orc_is_symmetric(_p(W), W.shape[0]))
 
 
+def ising_hamiltonian(edges, J, h, s) -> int:
+    """Eq. (1): H(S) = sum over edges of J_ij s_i s_j + sum_i h_i s_i
+    (s_i in {-1, +1}), summed edge by edge as written."""
+    s = np.asarray(s, dtype=np.int64)
+    H = 0
+    for (i, j), v in zip(np.asarray(edges).tolist(), np.asarray(J).tolist()):
+        H += int(v) * int(s[i]) * int(s[j])
+    return H + int(np.asarray(h, dtype=np.int64) @ s)
+
+
+def ising_qubo(n: int, edges, J, h):
+    """The QUBO of an Ising model under x_i = (s_i + 1) / 2 and the energy of
+    Eq. (2) summed over all ordered pairs: substituting s_i = 2 x_i - 1 into
+    Eq. (1), an edge term J s_i s_j = 4J x_i x_j - 2J x_i - 2J x_j + J and a
+    bias term h s_i = 2h x_i - h.  The quadratic part 4J x_i x_j is split
+    over the two ordered pairs (W_ij = W_ji = 2J), the linear parts go to the
+    diagonal (x_i^2 = x_i) and the constants to c, so that E(X) = H(S) + c
+    with c = sum h - sum J.  Edges with i == j or an index outside [0, n)
+    are skipped (returned as the count `skipped`).  Returns (W int64, c,
+    skipped)."""
+    W = np.zeros((n, n), dtype=np.int64)
+    c = 0
+    skipped = 0
+    for (i, j), v in zip(np.asarray(edges).reshape(-1, 2).tolist(), np.asarray(J).tolist()):
+        if i == j or not (0 <= i < n and 0 <= j < n):
+            skipped += 1
+            continue
+        W[i, j] += 2 * v
+        W[j, i] += 2 * v
+        W[i, i] -= 2 * v
+        W[j, j] -= 2 * v
+        c -= v
+    for i, v in enumerate(np.asarray(h).tolist()):
+        W[i, i] += 2 * v
+        c += v
+    return W, c, skipped
+
+
 def rank_index(u: int, m: int) -> int:
     return int(lib().orc_rank_index(u, m))
 

@@ -14,8 +14,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdabs.so")
 
-DABS_OK, DABS_E_INVALID, DABS_E_NOT_SYMMETRIC, DABS_E_RANGE, DABS_E_NOMEM, DABS_E_HIP, DABS_E_UNSUPPORTED = \
-    0, -1, -2, -3, -4, -5, -6
+DABS_OK, DABS_E_INVALID, DABS_E_NOT_SYMMETRIC, DABS_E_RANGE, DABS_E_NOMEM, DABS_E_HIP, DABS_E_UNSUPPORTED, \
+    DABS_E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
 DABS_W_I16, DABS_W_I32 = 0, 1
 (DABS_GREEDY, DABS_STRAIGHT, DABS_MAXMIN, DABS_CYCLICMIN, DABS_RANDOMMIN, DABS_POSITIVEMIN,
  DABS_TWONEIGHBOR, DABS_TABU_GREEDY) = range(8)
@@ -47,10 +47,12 @@ class dabs_ga_params(C.Structure):
                 ("p_explore", C.c_uint32), ("p_mutation", C.c_uint32), ("p_zero", C.c_uint32),
                 ("p_one", C.c_uint32), ("crossover_kind", C.c_int32), ("capacity", C.c_int32),
                 ("npools", C.c_int32), ("tau", C.c_int32), ("T", C.c_int32), ("Bn", C.c_int32),
-                ("greedy_cap", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64)]
+                ("greedy_cap", C.c_int32), ("flags", C.c_uint32), ("merge_hamming", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 DABS_SOLVER_TIME_WALK = 1
+DABS_GA_RESTART = 2
 
 
 # every function the header declares: name -> (argtypes, restype)
@@ -59,6 +61,12 @@ _SIGS = {
     "dabs_strerror": ([C.c_int], C.c_char_p),
     "dabs_last_error": ([], C.c_char_p),
     "dabs_max_n": ([C.c_int32], C.c_int32),
+    "dabs_max_bound": ([C.c_int32, C.c_int32], C.c_int64),
+    "dabs_ising_to_qubo": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int64, _P, _P], C.c_int),
+    "dabs_solver_record": ([_P, _P, _P, _P], C.c_int),
+    "dabs_solver_set_cancel": ([_P, _P], C.c_int),
+    "dabs_batched_record": ([_P, C.c_int32, _P, _P, _P], C.c_int),
+    "dabs_batched_set_cancel": ([_P, _P], C.c_int),
     "dabs_problem_create": ([_P, C.c_int32, C.c_int64, C.c_int32, _P, C.POINTER(_P)], C.c_int),
     "dabs_problem_destroy": ([_P], C.c_int),
     "dabs_problem_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
@@ -155,6 +163,26 @@ def dabs_max_n(wtype: int) -> int:
     return int(lib().dabs_max_n(wtype))
 
 
+def dabs_max_bound(wtype: int, n: int) -> int:
+    return int(lib().dabs_max_bound(wtype, n))
+
+
+def _host_ptr(t):
+    if t is None:
+        return None
+    if t.is_cuda or not t.is_pinned() or not t.is_contiguous():
+        raise ValueError("the flag must be a contiguous pinned host tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def dabs_ising_to_qubo(n: int, edges, J, h, W, offset, stream=None):
+    """edges [E][2] int32, J [E] int32, h [n] int32 (device); W [n][>=n] int32
+    output (row stride W.stride(0)); offset [2] int64 output."""
+    ne = 0 if edges is None else edges.shape[0]
+    _check(lib().dabs_ising_to_qubo(n, ne, _ptr(edges) if ne else None, _ptr(J) if ne else None, _ptr(h),
+                                    C.c_void_p(W.data_ptr()), W.stride(0), _ptr(offset), _stream(stream)))
+
+
 class Problem:
     """Handle of a loaded QUBO matrix (library-owned)."""
 
@@ -224,7 +252,7 @@ class Solver:
 
 def ga_params(*, T, Bn, tau=8, seed=0, capacity=100, npools=1, algos=MAIN_ALGOS, ops=tuple(range(8)),
               p_explore=214748365, p_mutation=1 << 29, p_zero=1 << 29, p_one=1 << 29, crossover_kind=0,
-              greedy_cap=0, flags=0) -> dabs_ga_params:
+              greedy_cap=0, flags=0, merge_hamming=0) -> dabs_ga_params:
     g = dabs_ga_params()
     g.n_algos = len(algos)
     for i, a in enumerate(algos):
@@ -235,6 +263,7 @@ def ga_params(*, T, Bn, tau=8, seed=0, capacity=100, npools=1, algos=MAIN_ALGOS,
     g.p_explore, g.p_mutation, g.p_zero, g.p_one = p_explore, p_mutation, p_zero, p_one
     g.crossover_kind, g.capacity, g.npools, g.tau = crossover_kind, capacity, npools, tau
     g.T, g.Bn, g.greedy_cap, g.seed, g.flags = T, Bn, greedy_cap, seed, flags
+    g.merge_hamming = merge_hamming
     return g
 
 
@@ -318,6 +347,26 @@ def dabs_batched_state(b: Batched, prob: int, x=None, e=None, phase=None, stream
 
 def dabs_batched_flips(b: Batched, out, stream=None):
     _check(lib().dabs_batched_flips(b.handle, _ptr(out), _stream(stream)))
+
+
+def dabs_solver_record(s: Solver, bits=None, out=None, stream=None):
+    """bits [nwords] int64, out [3] int64 = (energy, restarts, rounds)."""
+    _check(lib().dabs_solver_record(s.handle, _ptr(bits), _ptr(out), _stream(stream)))
+
+
+def dabs_solver_set_cancel(s: Solver, flag):
+    """flag: pinned host int32 tensor (torch.zeros(1, dtype=torch.int32, pin_memory=True)) or None."""
+    s.cancel_flag = flag            # keep it alive while attached
+    _check(lib().dabs_solver_set_cancel(s.handle, _host_ptr(flag)))
+
+
+def dabs_batched_record(b: Batched, prob: int, bits=None, out=None, stream=None):
+    _check(lib().dabs_batched_record(b.handle, prob, _ptr(bits), _ptr(out), _stream(stream)))
+
+
+def dabs_batched_set_cancel(b: Batched, flag):
+    b.cancel_flag = flag
+    _check(lib().dabs_batched_set_cancel(b.handle, _host_ptr(flag)))
 
 
 def dabs_batched_timing(b: Batched, reset: bool = False):

@@ -65,26 +65,32 @@ __device__ __forceinline__ uint64_t range_word(int lo, int hi, int w) {
 __device__ __forceinline__ uint32_t rank_index(uint32_t u, uint32_t m) { return scale32((uint32_t)cube_frac(u), m); }
 
 // Section IV-A: pools start with random vectors, energy +inf and random
-// algorithm / operation columns.  One thread per (pool, entry, word) of one
-// problem.
-__global__ void k_pool_init(BatchDev b, int p) {
-    const ProbDesc d = b.desc[p];
+// algorithm / operation columns.  Fill number `epoch` (0 at creation, e after
+// the e-th restart of merged pools, Section IV-B) draws the bits with Philox
+// sub-tag 2 epoch + 1 and the columns with 2 epoch.  Threads t0, t0 + step,
+// ... cover the (pool, entry, word) triples of one problem.
+__device__ void fill_pools(const BatchDev &b, const ProbDesc &d, uint32_t epoch, int64_t t0, int64_t step) {
     const int P = d.g.npools, m = d.g.capacity, nw = d.nw;
     const int64_t total = (int64_t)P * m * nw;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t tag = (uint32_t)TAG_POOL << 24;
+    for (int64_t t = t0; t < total; t += step) {
         const int w = (int)(t % nw);
         const int r = (int)((t / nw) % m);
         const int q = (int)(t / ((int64_t)nw * m));
         b.pool_bits[d.pool_word0 + t] =
-            rand_word(d.g.seed, (uint32_t)r, (uint32_t)q, ((uint32_t)TAG_POOL << 24) | 1u, w) & tail_mask(d.n, w);
+            rand_word(d.g.seed, (uint32_t)r, (uint32_t)q, tag | (2u * epoch + 1u), w) & tail_mask(d.n, w);
         if (w == 0) {
-            const R4 dr = philox((uint32_t)r, (uint32_t)q, 0, (uint32_t)TAG_POOL << 24, d.g.seed);
+            const R4 dr = philox((uint32_t)r, (uint32_t)q, 0, tag | (2u * epoch), d.g.seed);
             const int64_t cell = d.pool_cell0 + (int64_t)q * m + r;
             b.pool_e[cell] = E_INF;
             b.pool_algo[cell] = d.g.algos[scale32(dr.w[0], (uint32_t)d.g.n_algos)];
             b.pool_op[cell] = d.g.ops[scale32(dr.w[1], (uint32_t)d.g.n_ops)];
         }
     }
+}
+
+__global__ void k_pool_init(BatchDev b, int p) {
+    fill_pools(b, b.desc[p], 0u, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 // Target generation (Section IV-A, IV-B): one wave per global instance, lane
@@ -196,8 +202,14 @@ __device__ __forceinline__ int rule_rank(int a) {
 // piling up wherever the random choice of rules put it.  Only the launch
 // order changes: every item still runs once, and items are independent.
 // One workgroup per problem; item0[p] is the problem's first item.
+// It also latches the caller's cancel flag for the round: the later kernels
+// of the round read the latch, so a round runs entirely or not at all.
 __global__ __launch_bounds__(256) void k_sort_items(BatchDev b, int2 *items, const int *item0) {
     const int p = blockIdx.x;
+    if (p == 0 && threadIdx.x == 0)
+        b.ctr[3] = b.cancel ? (unsigned long long)(__hip_atomic_load(b.cancel, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                            : 0ull;
     const ProbDesc &d = b.desc[p];
     __shared__ int cnt[8];
     if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
@@ -227,6 +239,7 @@ __global__ __launch_bounds__(256) void k_sort_items(BatchDev b, int2 *items, con
 __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pools) {
     __shared__ long long se[POOL_MAX];
     __shared__ int sal[POOL_MAX], sop[POOL_MAX];
+    if (b.ctr[3]) return;                 // cancelled round: no packets
     const int2 pq = pools[blockIdx.x];
     const ProbDesc &d = b.desc[pq.x];
     const int q = pq.y, P = d.g.npools, m = d.g.capacity, nw = d.nw;
@@ -285,8 +298,64 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     }
 }
 
+// After the packets of a round (one workgroup per problem): the record (the
+// best rank-0 entry of the pools, lowest pool on ties, when it beats the
+// record) and, with DABS_GA_RESTART, the restart of merged pools (Section
+// IV-B): every entry evaluated and within Hamming distance merge_hamming of
+// the best entry -> a fresh fill of the pools.
+__global__ __launch_bounds__(256) void k_pool_record(BatchDev b) {
+    if (b.ctr[3]) return;
+    ProbDesc &d = b.desc[blockIdx.x];
+    const int P = d.g.npools, m = d.g.capacity, nw = d.nw;
+    const int tid = (int)threadIdx.x;
+    __shared__ int s_qb, s_merged;
+    if (tid == 0) {
+        int qb = 0;
+        for (int q = 1; q < P; ++q)
+            if (b.pool_e[d.pool_cell0 + (int64_t)q * m] < b.pool_e[d.pool_cell0 + (int64_t)qb * m]) qb = q;
+        s_qb = qb;
+        s_merged = 1;
+    }
+    __syncthreads();
+    const int64_t eb = b.pool_e[d.pool_cell0 + (int64_t)s_qb * m];
+    const uint64_t *best = b.pool_bits + d.pool_word0 + (int64_t)s_qb * m * nw;
+    const bool better = eb < d.record_e;
+    if (better)
+        for (int w = tid; w < nw; w += blockDim.x) b.record[d.rec_word0 + w] = best[w];
+    const uint32_t epoch = (uint32_t)d.epoch;
+    __syncthreads();                      // every thread has read record_e and epoch
+    if (better && tid == 0) d.record_e = eb;
+    if (!(d.g.flags & DABS_GA_RESTART)) return;
+    const int h = d.g.merge_hamming;
+    for (int c = tid; c < P * m; c += blockDim.x) {
+        bool far = b.pool_e[d.pool_cell0 + c] == E_INF;
+        const uint64_t *v = b.pool_bits + d.pool_word0 + (int64_t)c * nw;
+        int hd = 0;
+        for (int w = 0; w < nw && !far; ++w) hd += __popcll(v[w] ^ best[w]);
+        if (far || hd > h) atomicAnd(&s_merged, 0);
+    }
+    __syncthreads();
+    if (!s_merged) return;
+    __syncthreads();                      // every thread has read the pools' best entry
+    if (tid == 0) d.epoch = (int32_t)(epoch + 1);
+    fill_pools(b, d, epoch + 1, tid, blockDim.x);
+}
+
+// Round counter; a cancelled round does not count.
 __global__ void k_round_end(unsigned long long *ctr) {
-    if (threadIdx.x == 0) ctr[2] += 1;
+    if (threadIdx.x == 0 && !ctr[3]) ctr[2] += 1;
+}
+
+// Record of problem p: bits [nw], out [3] = (energy, restarts, rounds).
+__global__ void k_record_out(BatchDev b, int p, uint64_t *bits, int64_t *out) {
+    const ProbDesc &d = b.desc[p];
+    if (bits)
+        for (int w = threadIdx.x; w < d.nw; w += blockDim.x) bits[w] = b.record[d.rec_word0 + w];
+    if (out && threadIdx.x == 0) {
+        out[0] = d.record_e;
+        out[1] = d.epoch;
+        out[2] = (int64_t)b.ctr[2];
+    }
 }
 
 // Start of a run: clock, and per-problem targets and first-hit records.
@@ -304,7 +373,7 @@ __global__ void k_progress(BatchDev b, int nprob, int64_t *out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob) return;
     const ProbDesc &d = b.desc[p];
-    int64_t best = E_INF;
+    int64_t best = d.record_e;
     for (int q = 0; q < d.g.npools; ++q) {
         const int64_t e = b.pool_e[d.pool_cell0 + (int64_t)q * d.g.capacity];
         best = e < best ? e : best;
@@ -344,6 +413,7 @@ struct dabs_batched {
     bool graph_ready;
     int ttt;                           // time-to-target armed for the captured round
     bool armed;                        // a run armed targets; later runs continue its clock
+    const volatile int32_t *cancel_host;  // the caller's pinned cancel flag (nullable)
     // optional timing of the batch-search kernels (DABS_SOLVER_TIME_WALK)
     bool timed;
     static constexpr int NEV = 256;
@@ -368,7 +438,7 @@ static void batched_free(dabs_batched *s) {
         if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
     void *ptrs[] = {s->d.desc, s->d.pool_bits, s->d.pool_e, s->d.pool_algo, s->d.pool_op, s->d.x, s->d.target,
                     s->d.best, s->d.e, s->d.best_e, s->d.ph, s->d.algo, s->d.op, s->d.inst_prob, s->d.ctr,
-                    s->items, s->item0, s->pool_list};
+                    s->d.record, s->items, s->item0, s->pool_list};
     for (void *q : ptrs) (void)hipFree(q);
     (void)hipFree(s->mlp_cnt);
     (void)hipFree(s->mlp_feat);
@@ -403,7 +473,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
     dabs_batched *s = new dabs_batched();
     s->nprob = nprob;
     s->hdesc.resize(nprob);
-    int64_t inst = 0, cells = 0, pwords = 0, iwords = 0, pbits = 0;
+    int64_t inst = 0, cells = 0, pwords = 0, iwords = 0, pbits = 0, rwords = 0;
     for (int p = 0; p < nprob; ++p) {
         ProbDesc &d = s->hdesc[p];
         memset(&d, 0, sizeof(d));
@@ -418,6 +488,8 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         d.g = params[p];
         d.pool_cell0 = cells; d.pool_word0 = pwords; d.inst_word0 = iwords;
         d.target_e = INT64_MIN; d.hit = ~0ull;
+        d.rec_word0 = rwords; d.record_e = E_INF; d.epoch = 0;
+        rwords += d.nw;
         const int64_t pc = (int64_t)d.g.npools * d.g.capacity;
         inst += d.instances; cells += pc; pwords += pc * d.nw; iwords += (int64_t)d.instances * d.nw;
         pbits += pc * d.n;
@@ -469,7 +541,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
               hipMalloc(&d.best_e, 8 * (size_t)inst) == hipSuccess && hipMalloc(&d.ph, 4 * (size_t)inst) == hipSuccess &&
               hipMalloc(&d.algo, 4 * (size_t)inst) == hipSuccess && hipMalloc(&d.op, 4 * (size_t)inst) == hipSuccess &&
               hipMalloc(&d.inst_prob, 4 * (size_t)inst) == hipSuccess &&
-              hipMalloc(&d.ctr, 8 * 3) == hipSuccess &&
+              hipMalloc(&d.ctr, 8 * 4) == hipSuccess && hipMalloc(&d.record, 8 * (size_t)rwords) == hipSuccess &&
               hipMalloc(&s->items, sizeof(int2) * items.size()) == hipSuccess &&
               hipMalloc(&s->item0, sizeof(int) * nprob) == hipSuccess &&
               hipMalloc(&s->pool_list, sizeof(int2) * pl.size()) == hipSuccess;
@@ -497,7 +569,8 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
          hipMemsetAsync(d.x, 0, 8 * (size_t)iwords, st) == hipSuccess &&
          hipMemsetAsync(d.e, 0, 8 * (size_t)inst, st) == hipSuccess &&
          hipMemsetAsync(d.ph, 0, 4 * (size_t)inst, st) == hipSuccess &&
-         hipMemsetAsync(d.ctr, 0, 8 * 3, st) == hipSuccess;
+         hipMemsetAsync(d.ctr, 0, 8 * 4, st) == hipSuccess &&
+         hipMemsetAsync(d.record, 0, 8 * (size_t)rwords, st) == hipSuccess;
     for (int p = 0; p < nprob && ok; ++p) {
         const int64_t total = (int64_t)s->hdesc[p].g.npools * s->hdesc[p].g.capacity * s->hdesc[p].nw;
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
@@ -555,6 +628,8 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
     }
     hipLaunchKernelGGL(k_pool_insert, dim3(s->npool_list), dim3(64), 0, st, s->d, s->pool_list);
     HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_pool_record, dim3(s->nprob), dim3(256), 0, st, s->d);
+    HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, st, s->d.ctr);
     HIP_OK(hipGetLastError());
     return DABS_OK;
@@ -563,6 +638,7 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
 static int batched_run(dabs_batched *s, int rounds, const int64_t *target_e, int use_graph, hipStream_t st) {
     if (rounds < 0) return dabs_fail(DABS_E_INVALID, "rounds < 0");
     if (s->mlp_ops && !s->mlp) return dabs_fail(DABS_E_INVALID, "MLP operations enabled but no network attached");
+    if (s->cancel_host && *s->cancel_host) return dabs_fail(DABS_E_CANCELLED, "the cancel flag is set");
     if (target_e) {
         // arm: clock, targets and first-hit records restart here
         hipLaunchKernelGGL(k_run_begin, dim3((s->nprob + 255) / 256), dim3(256), 0, st, s->d, s->nprob, target_e);
@@ -654,6 +730,34 @@ int dabs_batched_state(const dabs_batched *s, int32_t prob, uint64_t *x_dev, int
     if (x_dev) HIP_OK(hipMemcpyAsync(x_dev, s->d.x + d.inst_word0, I * d.nw * 8, hipMemcpyDeviceToDevice, st));
     if (e_dev) HIP_OK(hipMemcpyAsync(e_dev, s->d.e + d.inst0, I * 8, hipMemcpyDeviceToDevice, st));
     if (phase_dev) HIP_OK(hipMemcpyAsync(phase_dev, s->d.ph + d.inst0, I * 4, hipMemcpyDeviceToDevice, st));
+    return DABS_OK;
+}
+
+int dabs_batched_record(const dabs_batched *s, int32_t prob, uint64_t *bits_dev, int64_t *out_dev, void *stream) {
+    if (!s || prob < 0 || prob >= s->nprob) return dabs_fail(DABS_E_INVALID, "bad batch or problem index");
+    hipLaunchKernelGGL(k_record_out, dim3(1), dim3(64), 0, (hipStream_t)stream, s->d, prob, bits_dev, out_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+int dabs_batched_set_cancel(dabs_batched *s, const volatile int32_t *flag_host) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
+    const int *dev = nullptr;
+    if (flag_host) {
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, (void *)flag_host, 0) != hipSuccess || !dp) {
+            (void)hipGetLastError();
+            return dabs_fail(DABS_E_INVALID, "the cancel flag must be pinned host memory (hipHostMalloc)");
+        }
+        dev = (const int *)dp;
+    }
+    s->cancel_host = flag_host;
+    s->d.cancel = dev;
+    if (s->graph_ready) {            // the captured round has the old kernel arguments
+        (void)hipGraphExecDestroy(s->exec);
+        (void)hipGraphDestroy(s->graph);
+        s->graph_ready = false;
+    }
     return DABS_OK;
 }
 
@@ -859,6 +963,16 @@ int dabs_solver_state(const dabs_solver *s, uint64_t *x_dev, int64_t *e_dev, uin
 int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
     return dabs_batched_progress(s->b, out_dev, stream);
+}
+
+int dabs_solver_record(const dabs_solver *s, uint64_t *bits_dev, int64_t *out_dev, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_record(s->b, 0, bits_dev, out_dev, stream);
+}
+
+int dabs_solver_set_cancel(dabs_solver *s, const volatile int32_t *flag_host) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_set_cancel(s->b, flag_host);
 }
 
 int dabs_solver_timing(dabs_solver *s, double *out_host, int32_t reset) {

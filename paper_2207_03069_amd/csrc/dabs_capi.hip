@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "dabs_internal.h"
 #include "dabs_device.h"
 
@@ -26,10 +28,14 @@ int dabs_fail(int status, const char *fmt, ...) {
 
 namespace dabs {
 
+// largest |W_ij| (i != j) of int32 W: operand range of the 24-bit multiply
+constexpr long long I24_MAX = (1 << 23) - 1;
+
 // Symmetry and delta bound of the caller's W: one block per row i; every
 // thread compares its W_ij with W_ji and sums |W_ij| (counted twice off the
 // diagonal).  bad: bit 0 asymmetric, bit 1 an int16 -32768 off the diagonal
-// (the search negates off-diagonal int16 weights in 16 bits).
+// (the search negates off-diagonal int16 weights in 16 bits), bit 2 an int32
+// weight off the diagonal outside the 24-bit multiply's operand range.
 template <typename WT>
 __global__ __launch_bounds__(256) void k_validate(const WT *__restrict__ W, int64_t ld, int n,
                                                   int *__restrict__ bad, long long *__restrict__ rowb) {
@@ -40,6 +46,7 @@ __global__ __launch_bounds__(256) void k_validate(const WT *__restrict__ W, int6
         const long long a = W[(int64_t)i * ld + j], b = W[(int64_t)j * ld + i];
         asym |= a != b;
         if (sizeof(WT) == 2 && j != i && a == -32768) asym |= 2;
+        if (sizeof(WT) == 4 && j != i && (a > I24_MAX || a < -I24_MAX)) asym |= 4;
         acc += (j == i ? 1 : 2) * (a < 0 ? -a : a);
     }
     __shared__ long long part[256];
@@ -100,6 +107,44 @@ __global__ __launch_bounds__(256) void k_energy(const WT *__restrict__ W, const 
     if (lane == 0) e[wid] = acc;
 }
 
+// Ising front-end (Eq. (1) -> Eq. (2)): clear the n x n block, then every
+// edge and bias adds its terms with integer atomics (order-free, so exact).
+__global__ __launch_bounds__(256) void k_clear_block(int32_t *__restrict__ W, int64_t ld, int n,
+                                                     long long *__restrict__ off) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+        W[(t / n) * ld + t % n] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 2) off[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_ising_edges(int n, int64_t ne, const int32_t *__restrict__ edges,
+                                                     const int32_t *__restrict__ J, int32_t *__restrict__ W,
+                                                     int64_t ld, long long *__restrict__ off) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = edges[2 * e], j = edges[2 * e + 1];
+        if (i == j || i < 0 || j < 0 || i >= n || j >= n) {
+            atomicAdd((unsigned long long *)&off[1], 1ull);
+            continue;
+        }
+        const int v = J[e];
+        // s_i s_j = 4 x_i x_j - 2 x_i - 2 x_j + 1: W_ij = W_ji = 2J, W_ii and W_jj lose 2J, c loses J
+        atomicAdd(&W[(int64_t)i * ld + j], 2 * v);
+        atomicAdd(&W[(int64_t)j * ld + i], 2 * v);
+        atomicAdd(&W[(int64_t)i * ld + i], -2 * v);
+        atomicAdd(&W[(int64_t)j * ld + j], -2 * v);
+        atomicAdd((unsigned long long *)&off[0], (unsigned long long)(-(long long)v));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ising_bias(int n, const int32_t *__restrict__ h, int32_t *__restrict__ W,
+                                                    int64_t ld, long long *__restrict__ off) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // h_i s_i = 2 h_i x_i - h_i
+    atomicAdd(&W[(int64_t)i * ld + i], 2 * h[i]);
+    atomicAdd((unsigned long long *)&off[0], (unsigned long long)(long long)h[i]);
+}
+
 }  // namespace dabs
 
 using namespace dabs;
@@ -111,7 +156,8 @@ const char *dabs_strerror(int status) {
     case DABS_OK: return "ok";
     case DABS_E_INVALID: return "invalid argument";
     case DABS_E_NOT_SYMMETRIC: return "W is not symmetric";
-    case DABS_E_RANGE: return "W exceeds the exact device range (delta bound >= 2^23 - 1)";
+    case DABS_E_RANGE: return "W exceeds the exact device range (delta bound above dabs_max_bound, or a weight out of range)";
+    case DABS_E_CANCELLED: return "cancelled by the caller's flag";
     case DABS_E_NOMEM: return "device allocation failed";
     case DABS_E_HIP: return "HIP runtime error";
     case DABS_E_UNSUPPORTED: return "size not supported by this build";
@@ -122,6 +168,11 @@ const char *dabs_strerror(int status) {
 const char *dabs_last_error(void) { return g_err; }
 
 int32_t dabs_max_n(int32_t wtype) { return dabs::max_n(wtype); }
+
+int64_t dabs_max_bound(int32_t wtype, int32_t n) {
+    if ((wtype != DABS_W_I16 && wtype != DABS_W_I32) || n < 1 || n > dabs::max_n(wtype)) return -1;
+    return ((int64_t)1 << (29 - key_shift(wtype, walk_slots(wtype, n)))) - 2;
+}
 
 int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype, void *stream,
                         dabs_problem **out) {
@@ -146,7 +197,7 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     int *diag = nullptr;
     if (hipMalloc(&bad, sizeof(int)) != hipSuccess || hipMalloc(&rowb, sizeof(long long) * n) != hipSuccess ||
         hipMalloc(&Wp, es * (size_t)n * (size_t)ldp) != hipSuccess || hipMalloc(&diag, sizeof(int) * n) != hipSuccess) {
-        hipFree(bad); hipFree(rowb); hipFree(Wp); hipFree(diag);
+        (void)hipFree(bad); (void)hipFree(rowb); (void)hipFree(Wp); (void)hipFree(diag);
         return dabs_fail(DABS_E_NOMEM, "allocating %zu bytes for W", es * (size_t)n * (size_t)ldp);
     }
     int status = DABS_OK;
@@ -169,8 +220,11 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     if (status == DABS_OK && (hbad & 1)) status = dabs_fail(DABS_E_NOT_SYMMETRIC, "W is not symmetric");
     if (status == DABS_OK && (hbad & 2))
         status = dabs_fail(DABS_E_RANGE, "int16 W holds -32768 off the diagonal (pass it as int32)");
-    if (status == DABS_OK && bound >= (1 << 23) - 1)
-        status = dabs_fail(DABS_E_RANGE, "delta bound %lld >= 2^23 - 1", bound);
+    if (status == DABS_OK && (hbad & 4))
+        status = dabs_fail(DABS_E_RANGE, "int32 W holds an off-diagonal weight outside [-(2^23-1), 2^23-1]");
+    const long long maxb = dabs_max_bound(wtype, n);
+    if (status == DABS_OK && bound > maxb)
+        status = dabs_fail(DABS_E_RANGE, "delta bound %lld above %lld for n = %d", bound, maxb, n);
     if (status == DABS_OK) {
         const int gx = (int)((ldp + 255) / 256);
         if (wtype == DABS_W_I16)
@@ -184,11 +238,11 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     } else if (status == DABS_E_HIP) {
         dabs_fail(DABS_E_HIP, "validating W failed");
     }
-    hipFree(bad);
+    (void)hipFree(bad);
     if (status != DABS_OK) {
-        hipFree(rowb);
-        hipFree(Wp);
-        hipFree(diag);
+        (void)hipFree(rowb);
+        (void)hipFree(Wp);
+        (void)hipFree(diag);
         return status;
     }
     dabs_problem *p = new dabs_problem;
@@ -234,6 +288,27 @@ int dabs_energy(const dabs_problem *p, const uint64_t *x_dev, int32_t count, int
     else
         hipLaunchKernelGGL(k_energy<int32_t>, dim3(blocks), dim3(256), 0, st, (const int32_t *)p->W, p->diag, p->ld,
                            p->n, nw, x_dev, count, e_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+int dabs_ising_to_qubo(int32_t n, int64_t nedges, const int32_t *edges_dev, const int32_t *J_dev,
+                       const int32_t *h_dev, int32_t *W_dev, int64_t ld, int64_t *offset_dev, void *stream) {
+    if (n < 1 || ld < n || nedges < 0) return dabs_fail(DABS_E_INVALID, "need n >= 1, ld >= n, nedges >= 0");
+    if (!h_dev || !W_dev || !offset_dev || (nedges > 0 && (!edges_dev || !J_dev)))
+        return dabs_fail(DABS_E_INVALID, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    long long *off = (long long *)offset_dev;
+    const int64_t cells = (int64_t)n * n;
+    const unsigned cb = (unsigned)std::min<int64_t>((cells + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_clear_block, dim3(cb), dim3(256), 0, st, W_dev, ld, n, off);
+    HIP_OK(hipGetLastError());
+    if (nedges > 0) {
+        const unsigned eb = (unsigned)std::min<int64_t>((nedges + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_ising_edges, dim3(eb), dim3(256), 0, st, n, nedges, edges_dev, J_dev, W_dev, ld, off);
+        HIP_OK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_ising_bias, dim3((n + 255) / 256), dim3(256), 0, st, n, h_dev, W_dev, ld, off);
     HIP_OK(hipGetLastError());
     return DABS_OK;
 }

@@ -20,9 +20,6 @@
 namespace dabs {
 
 constexpr int WAVE = 64;
-// above every delta (|Delta| <= B < 2^23 - 1): PositiveMin's threshold when no
-// delta of the domain is positive
-constexpr int H_PAD = (1 << 23) - 1;
 constexpr int TAU_MAX = 16;
 constexpr int64_t E_INF = INT64_MAX;
 

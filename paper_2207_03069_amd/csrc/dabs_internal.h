@@ -50,6 +50,15 @@ hipError_t launch_walk(const dabs_problem *p, const WalkArgs &a, hipStream_t str
 
 // Slot count (power of two) of the walker kernel that serves n bits.
 int walk_slots(int wtype, int n);
+// Shift K of the walker's key words (delta 2^K + local index) for a weight
+// type and slot count: valid keys stay in (-2^29, 2^29) while |delta| <=
+// 2^(29-K) - 2.
+inline int key_shift(int wtype, int slots) {
+    const int v = wtype == DABS_W_I16 ? 8 : 4, logv = wtype == DABS_W_I16 ? 3 : 2;
+    int k = 0;
+    while ((1 << k) < v * slots) ++k;
+    return k < logv ? logv : k;
+}
 
 // ---------------------------------------------------------------- batches
 // One problem of a batch as the device sees it.  Per-instance arrays of all
@@ -68,6 +77,10 @@ struct ProbDesc {
     dabs_ga_params g;
     int64_t target_e;              // time-to-target energy; INT64_MIN when unset
     unsigned long long hit;        // ticks of the first E(BEST) <= target_e (atomicMin)
+    int64_t rec_word0;             // first word of the problem's record vector
+    int64_t record_e;              // energy of the record (E_INF before the first round)
+    int32_t epoch;                 // restarts of merged pools so far
+    int32_t pad_;
 };
 
 struct BatchDev {
@@ -81,7 +94,9 @@ struct BatchDev {
     int32_t *algo, *op;
     int32_t *inst_prob;            // global instance -> problem
     const float *pool_logits;      // nullable: learned logits of every pooled bit
-    unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round
+    unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round, [3] round cancelled
+    uint64_t *record;              // per problem: best pooled vector of the run (kept across restarts)
+    const int *cancel;             // nullable: device view of the caller's pinned cancel flag
 };
 
 // Batch search of a list of (problem, instance) items, one wavefront each.

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     vecH kb0, kb1, mul0, mul1;
     const int lane = lane_id();
     const BatchDev &b = a.b;
+    if (b.ctr[3]) return;                 // the round is cancelled (latched before the launch)
     const int2 item = a.items[blockIdx.x];
     const int p = __builtin_amdgcn_readfirstlane(item.x), i = __builtin_amdgcn_readfirstlane(item.y);
     ProbDesc *d = b.desc + p;

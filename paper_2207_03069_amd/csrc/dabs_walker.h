@@ -16,7 +16,8 @@
 //   least key of all bits     = per lane min(unsigned min, signed min & ~2^31),
 //     since the signed minimum of a lane is its least excluded word when it
 //     has one.
-// Valid keys lie in (-2^29, 2^29) (|Delta| < 2^23, KB <= 6), so valid
+// Valid keys lie in (-2^29, 2^29) (|Delta| <= 2^(29-KB) - 2, checked at the
+// problem load), so valid
 // unexcluded words lie in (0, 2^30) and anything at or above 2^30 is "none".
 // The tabu of R11 (bit flipped at iteration t excluded at t+1 .. t+tau) is
 // set on the flip and cleared tau+1 iterations later from a 32-entry ring
@@ -104,6 +105,9 @@ struct Walker {
     static constexpr int LOGV = V == 8 ? 3 : 2;
     static constexpr int EPL = V * SLOTS;
     static constexpr int KB = clog2(EPL) < LOGV ? LOGV : clog2(EPL);
+    // largest |delta| the problem load admits at this key shift; PositiveMin's
+    // threshold when no delta of its domain is positive (every key qualifies)
+    static constexpr int D_TOP = (1 << (29 - KB)) - 2;
     static constexpr int SB = KB - LOGV;
     static constexpr int SPAN = WAVE * V;   // bits covered by one slot
     // wave reductions run on kb >> LOGV (key order down to the slot; the lane
@@ -728,7 +732,7 @@ struct Walker {
                 for (int j = 0; j < EPL; ++j) kp = min(kp, ((uint32_t)kb[j] & 0x7FFFFFFFu) - C);
             }
             const int mw = wave_min(wv(kp));
-            const int d = none(mw) ? H_PAD - 1 : (mw >> SB) + 1;
+            const int d = none(mw) ? D_TOP : (mw >> SB) + 1;
             const int dk = d * (1 << KB) + ((1 << KB) - 1);
             const int c = (t - 1) >> 2;
             if (c >= cbase + 64) {

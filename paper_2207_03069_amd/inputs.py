@@ -109,6 +109,84 @@ def tsp_instance(ncity: int = 32, seed: int = 0):
     return tsp_qubo(D, A), D, A
 
 
+def qap_instance(nfac: int, seed: int, lo: int = 0, hi: int = 99):
+    """A symmetric QAP of nfac facilities (Section II-B): flows l(i, j) and
+    distances d(i, j) uniform integers in [lo, hi] for i < j, mirrored, zero
+    diagonals (the uniform random shape of Taillard's tai*a instances).  Draw
+    order: one nfac x nfac flow matrix, then one distance matrix, upper parts
+    kept.  Returns (flow, dist) int64."""
+    rng = np.random.default_rng(seed)
+    F = np.triu(rng.integers(lo, hi + 1, size=(nfac, nfac), dtype=np.int64), 1)
+    D = np.triu(rng.integers(lo, hi + 1, size=(nfac, nfac), dtype=np.int64), 1)
+    return F + F.T, D + D.T
+
+
+def qap_qubo(flow: np.ndarray, dist: np.ndarray, p: int, dtype=np.int32) -> np.ndarray:
+    """The one-hot QUBO of Section II-B: bit <i, j> = i * n + j (facility i at
+    location j); W = l(i, i') d(j, j') for i != i' and j != j', -p on the
+    diagonal, p for two bits sharing exactly one of facility and location.
+    A feasible X has E(X) = C(g_X) - n p."""
+    n = flow.shape[0]
+    N = n * n
+    W = np.einsum("ac,bd->abcd", flow.astype(np.int64), dist.astype(np.int64)).reshape(N, N)
+    fi = np.repeat(np.arange(n), n)
+    lj = np.tile(np.arange(n), n)
+    same_f = fi[:, None] == fi[None, :]
+    same_l = lj[:, None] == lj[None, :]
+    W[same_f != same_l] = p
+    W[same_f & same_l] = -p
+    return W.astype(dtype)
+
+
+def qap_cost(flow: np.ndarray, dist: np.ndarray, g) -> int:
+    """C(g) = sum_{i, j} l(i, j) d(g(i), g(j))."""
+    g = np.asarray(g)
+    return int((flow * dist[np.ix_(g, g)]).sum())
+
+
+def sparse_graph(n: int, m: int, max_degree: int, seed: int):
+    """m distinct undirected edges on n nodes, every degree <= max_degree:
+    candidate pairs (i, j), i != j, drawn uniformly in batches of 4m; a pair
+    is kept when new and both ends are below the cap.  Returns edges int64
+    [m, 2] with i < j.  Stands in for a quantum annealer's sparse hardware
+    graph (Section II-C: 5,627 nodes, 40,279 edges; degree at most 15)."""
+    rng = np.random.default_rng(seed)
+    deg = np.zeros(n, dtype=np.int64)
+    seen = set()
+    out = []
+    while len(out) < m:
+        cand = rng.integers(0, n, size=(4 * m, 2))
+        for i, j in cand.tolist():
+            if len(out) == m:
+                break
+            if i == j:
+                continue
+            a, b = (i, j) if i < j else (j, i)
+            if (a, b) in seen or deg[a] >= max_degree or deg[b] >= max_degree:
+                continue
+            seen.add((a, b))
+            deg[a] += 1
+            deg[b] += 1
+            out.append((a, b))
+    return np.array(out, dtype=np.int64).reshape(-1, 2)
+
+
+def ising_instance(n: int, edges: np.ndarray, r: int, seed: int):
+    """A random Ising model of resolution r (Section II-C): every J_ij uniform
+    over the nonzero integers in [-r, r] and every h_i over the nonzero
+    integers in [-4r, 4r].  Draw order: J (one per edge), then h.  Returns
+    (J int64 [m], h int64 [n])."""
+    rng = np.random.default_rng(seed)
+
+    def nonzero(k, size):
+        v = rng.integers(1, k + 1, size=size)
+        return np.where(rng.integers(0, 2, size=size) == 1, v, -v).astype(np.int64)
+
+    J = nonzero(r, len(edges))
+    h = nonzero(4 * r, n)
+    return J, h
+
+
 def batched_sizes(count: int = 256, lo: int = 256, ratio: int = 16, seed: int = 0) -> np.ndarray:
     """Problem sizes n = floor(lo * ratio^U), U ~ U[0,1), for the many-problem
     workload (log-uniform in [256, 4096))."""

@@ -230,6 +230,73 @@ def test_solver_with_learned_operations_exact_energies():
         assert oracle.energy(W, x[i]) == e[i]
 
 
+def exact_ga_network():
+    """A network whose every product and sum is exact in bfloat16 / float32
+    on pools of capacity 8:  z = |f1 - f6| + f4/4 + 3 f7/4 - 5/4.  The logit
+    is positive where the bit differs from the pool's best entry, and also
+    where it agrees but most of the pool has the bit set in a low-ranked
+    entry, so both learned operations draw non-trivial targets, and both
+    sides compute the same logits to the last bit."""
+    d = dict(W1=np.zeros((64, 8)), b1=np.zeros(64), W2=np.zeros((64, 64)), b2=np.zeros(64),
+             W3=np.zeros(64), b3=np.array([-1.25]))
+    d["W1"][0, 1], d["W1"][0, 6] = 1.0, -1.0       # relu(f1 - f6)
+    d["W1"][1, 1], d["W1"][1, 6] = -1.0, 1.0       # relu(f6 - f1)
+    d["W1"][2, 4] = 1.0                            # relu(f4)
+    d["W1"][3, 4] = -1.0                           # relu(-f4)
+    d["W1"][4, 7] = 1.0                            # f7 >= 0
+    for u in range(5):
+        d["W2"][u, u] = 1.0
+    d["W3"][:5] = [1.0, 1.0, 0.25, -0.25, 0.75]
+    return omlp.pack(d).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,wt,ops", [(90, np.int16, tuple(range(10))), (70, np.int32, (8, 9, 2)),
+                                      (130, np.int16, (8, 9))])
+def test_learned_ga_bit_exact_with_oracle(n, wt, ops):
+    """The learned operations inside device rounds (pool scoring, parent
+    logits, MLP-seed / MLP-mutate targets) against the oracle's generational
+    loop with the same network: pools, states and energies bit for bit."""
+    W = inputs.dense_qubo(n, -100, 100, 21 + n, dtype=wt)
+    params = exact_ga_network()
+    inst, P, m, rounds, seed = 16, 2, 8, 4, 5
+    g = dabs.ga_params(T=max(1, n // 8), Bn=2 * n, tau=8, seed=seed, capacity=m, npools=P, ops=ops,
+                       greedy_cap=100000)
+    p = dabs.dabs_problem_create(dev(W))
+    s = dabs.dabs_solver_create(p, g, inst)
+    net = dabs.dabs_mlp_create(params)
+    dabs.dabs_solver_set_mlp(s, net)
+    dabs.dabs_solver_run(s, rounds)
+    nw = (n + 63) // 64
+    bits = torch.zeros((P, m, nw), dtype=torch.int64, device=DEV)
+    pe = torch.zeros((P, m), dtype=torch.int64, device=DEV)
+    po = torch.zeros((P, m), dtype=torch.int32, device=DEV)
+    x = torch.zeros((inst, nw), dtype=torch.int64, device=DEV)
+    e = torch.zeros(inst, dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_pools(s, bits, pe, None, po)
+    dabs.dabs_solver_state(s, x, e)
+    torch.cuda.synchronize()
+    used = []
+
+    def score(rnd, pool_bits):
+        used.append(rnd)
+        return omlp.pool_logits(params, W, pool_bits)
+
+    ref = oracle.solve(W, oracle.ga_params(T=g.T, Bn=g.Bn, tau=8, seed=seed, capacity=m, npools=P, ops=ops,
+                                           greedy_cap=100000), inst, rounds, score=score)
+    assert used == list(range(rounds))
+    assert np.array_equal(pe.cpu().numpy(), ref["pool_e"])
+    assert np.array_equal(inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), ref["pool_bits"])
+    assert np.array_equal(po.cpu().numpy(), ref["pool_op"])
+    assert np.array_equal(inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), ref["x"])
+    assert np.array_equal(e.cpu().numpy(), ref["e"])
+    # the learned operations produced pooled entries (not only initial columns)
+    fin = ref["pool_e"] < np.iinfo(np.int64).max
+    assert np.isin(ref["pool_op"][fin], (8, 9)).any()
+    dabs.dabs_solver_destroy(s)
+    dabs.dabs_mlp_destroy(net)
+    dabs.dabs_problem_destroy(p)
+
+
 def test_solver_with_network_attached_but_plain_operations_is_exact():
     """Attaching a network changes nothing while the learned operations are
     disabled: bit-exact with the oracle."""

@@ -194,7 +194,7 @@ def test_problem_errors():
     with pytest.raises(dabs.DabsError) as ei:
         load(W)
     assert ei.value.status == dabs.DABS_E_NOT_SYMMETRIC
-    big = np.full((64, 64), 100000, np.int32)
+    big = np.full((64, 64), 2000000, np.int32)     # B = 127 * 2e6 > 2^27 - 2, the bound at n = 64 int32
     with pytest.raises(dabs.DabsError) as ei:
         load(big)
     assert ei.value.status == dabs.DABS_E_RANGE
