@@ -368,6 +368,24 @@ int dabs_ising_to_qubo(int32_t n, int64_t nedges, const int32_t *edges_dev, cons
                        const int32_t *h_dev, int32_t *W_dev, int64_t ld, int64_t *offset_dev, void *stream);
 
 /*
+ * Read-bandwidth probe of one memory level of the current device, for
+ * setting the search kernels' achieved bandwidth against a measured peak:
+ * a streaming kernel reads with 16-byte loads per lane (the walker's access
+ * width), on every compute unit, from
+ *   DABS_PROBE_HBM   a 4 GiB buffer, one pass (larger than the Infinity Cache),
+ *   DABS_PROBE_MALL  a 128 MiB buffer (fits the 256 MB Infinity Cache),
+ *   DABS_PROBE_L2    a 2 MiB buffer (fits each XCD's 4 MB L2, not the 32 KB
+ *                    vector caches: the re-reads are shifted every pass so that
+ *                    no compute unit re-reads its own chunks),
+ *   DABS_PROBE_LDS   64 KB of LDS per workgroup, 256 passes.
+ * out_host[3] = (GB/s of the fastest of three timed launches, bytes read per
+ * launch, its milliseconds).  Allocates and frees its own buffers and
+ * synchronises the device.  Errors: DABS_E_INVALID, DABS_E_NOMEM, DABS_E_HIP.
+ */
+enum { DABS_PROBE_HBM = 0, DABS_PROBE_MALL = 1, DABS_PROBE_L2 = 2, DABS_PROBE_LDS = 3 };
+int dabs_bandwidth_probe(int32_t level, double *out_host);
+
+/*
  * Learned proposal.  Not in the paper: a small network that scores every bit
  * of a pooled vector and two genetic operations that use the scores; the
  * exact search of Section III stays the judge (energies are never

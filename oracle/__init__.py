@@ -104,7 +104,7 @@ def lib():
         L.orc_solve.argtypes = [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, i32]
         L.orc_solve.restype = i64
         L.orc_solve_ex.argtypes = [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, i32,
-                                   SCORE_FN, P, P, P, P]
+                                   SCORE_FN, P, P, P, P, P]
         L.orc_solve_ex.restype = i64
         L.orc_target_from_pools.argtypes = [i32, P, P, P, P, P, P, u32, u32, P, P, P]
         L.orc_randmin_q.argtypes = [i64, i64, i32]
@@ -256,22 +256,34 @@ def batch_search(W, rule, x0, target, *, T, Bn, tau=0, seed=0, inst=0, ph=0,
                 trace=trace[:min(f, trace_cap)] if trace_cap else None)
 
 
-def solve(W, g: GAParams, instances: int, rounds: int, verify=False, score=None):
+def solve(W, g: GAParams, instances: int, rounds: int, verify=False, score=None, tick=None):
     """Generational DABS loop; returns pools, per-instance state, insert log,
     the best pooled vector over the run (kept across restarts) and the number
     of restarts.  score(round, pool_bits [P][m][n] uint8) -> float32 logits
     [P][m][n] gives the learned scores of every pooled bit at the start of a
-    round (the MLP operations copy their parent without it)."""
+    round (the MLP operations copy their parent without it); tick(round),
+    optional, is called at the start of every round; round_best holds the
+    record's energy after each round."""
     W = _w(W)
     n = W.shape[0]
     P, m = g.npools, g.capacity
     cb = SCORE_FN()
     if score is not None:
         def _cb(ctx, rnd, bits, out):
+            if tick is not None:
+                tick(int(rnd))
             pb = np.ctypeslib.as_array(bits, shape=(P, m, n)).copy()
             z = np.ascontiguousarray(np.asarray(score(int(rnd), pb), dtype=np.float32).reshape(P * m * n))
             np.ctypeslib.as_array(out, shape=(P * m * n,))[:] = z
         cb = SCORE_FN(_cb)
+    elif tick is not None:
+        if any(o in (OP_MLP_SEED, OP_MLP_MUTATE) for o in g.ops[:g.n_ops]):
+            raise ValueError("tick without score: the learned operations need scores")
+
+        def _tick(ctx, rnd, bits, out):   # the scores are left unset: no learned operation is enabled
+            tick(int(rnd))
+        cb = SCORE_FN(_tick)
+    rb = np.zeros(max(rounds, 1), dtype=np.int64)
     pb = np.zeros((P, m, n), dtype=np.uint8)
     pe = np.zeros((P, m), dtype=np.int64)
     pa = np.zeros((P, m), dtype=np.int32)
@@ -287,12 +299,12 @@ def solve(W, g: GAParams, instances: int, rounds: int, verify=False, score=None)
     nr = C.c_int32()
     f = lib().orc_solve_ex(_p(W), n, C.byref(g), instances, rounds, _p(pb), _p(pe), _p(pa), _p(po),
                            _p(x), _p(e), _p(ph), _p(ins), _p(tg), _p(pk), int(verify), cb, None,
-                           _p(bb), C.byref(be), C.byref(nr))
+                           _p(bb), C.byref(be), C.byref(nr), _p(rb))
     if f < 0:
         raise RuntimeError("oracle solve failed (%d)" % f)
     return dict(flips=int(f), pool_bits=pb, pool_e=pe, pool_algo=pa, pool_op=po, x=x, e=e, ph=ph,
                 inserts=ins[:rounds], targets=tg, packets=pk, best_bits=bb, best_e=int(be.value),
-                restarts=int(nr.value))
+                restarts=int(nr.value), round_best=rb[:rounds])
 
 
 def target_from_pools(g: GAParams, pool_bits, inst, rnd=0, pool_e=None, pool_algo=None, pool_op=None,

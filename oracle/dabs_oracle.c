@@ -841,14 +841,15 @@ static int pools_merged(const pools_t *p, int32_t h)
  * MLP-seed / MLP-mutate operations use (R22).  With ORC_GA_RESTART set in
  * g->flags the pools restart when merged (R24); best_bits / best_e (nullable)
  * receive the best pooled vector seen over all rounds and epochs and
- * restarts_out the number of restarts.  Returns total flips or a negative
+ * restarts_out the number of restarts; round_best (nullable, [rounds]) the
+ * record's energy after each round.  Returns total flips or a negative
  * code. */
 int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t instances,
                      int32_t rounds, uint8_t *pool_bits, int64_t *pool_e, int32_t *pool_algo,
                      int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
                      int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify,
                      orc_score_fn score, void *score_ctx, uint8_t *best_bits, int64_t *best_e,
-                     int32_t *restarts_out)
+                     int32_t *restarts_out, int64_t *round_best)
 {
     if (n < 1 || instances < 1 || g->npools < 1 || g->capacity < 1) return -1;
     if (g->n_algos < 1 || g->n_ops < 1) return -1;
@@ -895,6 +896,7 @@ int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_
                 record_e = p.e[(int64_t)q * p.cap];
                 memcpy(record, entry_bits(&p, q, 0), (size_t)n);
             }
+        if (round_best) round_best[r] = record_e;
         if ((g->flags & ORC_GA_RESTART) && pools_merged(&p, g->merge_hamming)) {
             epoch++;
             pools_init(&p, g, epoch);
@@ -918,7 +920,7 @@ int64_t orc_solve(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t i
 {
     return orc_solve_ex(W, n, g, instances, rounds, pool_bits, pool_e, pool_algo, pool_op, x_out,
                         e_out, ph_out, inserts, targets_out, packets_out, verify, NULL, NULL, NULL,
-                        NULL, NULL);
+                        NULL, NULL, NULL);
 }
 
 /* One target drawn by ga_target from pools the caller supplies (bits

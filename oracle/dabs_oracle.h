@@ -80,7 +80,7 @@ int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_
                      int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
                      int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify,
                      orc_score_fn score, void *score_ctx, uint8_t *best_bits, int64_t *best_e,
-                     int32_t *restarts_out);
+                     int32_t *restarts_out, int64_t *round_best);
 
 void orc_target_from_pools(int32_t n, const orc_ga_params *g, uint8_t *pool_bits, int64_t *pool_e,
                            int32_t *pool_algo, int32_t *pool_op, const float *logits, uint32_t round,

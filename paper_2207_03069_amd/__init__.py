@@ -62,6 +62,7 @@ _SIGS = {
     "dabs_last_error": ([], C.c_char_p),
     "dabs_max_n": ([C.c_int32], C.c_int32),
     "dabs_max_bound": ([C.c_int32, C.c_int32], C.c_int64),
+    "dabs_bandwidth_probe": ([C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "dabs_ising_to_qubo": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "dabs_solver_record": ([_P, _P, _P, _P], C.c_int),
     "dabs_solver_set_cancel": ([_P, _P], C.c_int),
@@ -161,6 +162,16 @@ def dabs_last_error() -> str:
 
 def dabs_max_n(wtype: int) -> int:
     return int(lib().dabs_max_n(wtype))
+
+
+DABS_PROBE_HBM, DABS_PROBE_MALL, DABS_PROBE_L2, DABS_PROBE_LDS = range(4)
+
+
+def dabs_bandwidth_probe(level: int):
+    """(GB/s, bytes per launch, ms per launch) of the read probe of a level."""
+    out = (C.c_double * 3)()
+    _check(lib().dabs_bandwidth_probe(level, out))
+    return out[0], out[1], out[2]
 
 
 def dabs_max_bound(wtype: int, n: int) -> int:
