@@ -46,7 +46,9 @@ typedef enum {
     DABS_E_CANCELLED = -7       /* the caller's cancel flag is set (see dabs_solver_set_cancel) */
 } dabs_status;
 
-typedef enum { DABS_W_I16 = 0, DABS_W_I32 = 1 } dabs_wtype;
+/* Weight types: dense int16 or int32 W (dabs_problem_create), or sparse
+ * (dabs_problem_create_csr). */
+typedef enum { DABS_W_I16 = 0, DABS_W_I32 = 1, DABS_W_SPARSE = 2 } dabs_wtype;
 
 /* Search rules: Section III-A (Greedy, Straight, MaxMin, CyclicMin,
  * RandomMin, PositiveMin, TwoNeighbor) and tabu greedy (T iterations, each
@@ -101,6 +103,27 @@ int64_t dabs_max_bound(int32_t wtype, int32_t n);
  */
 int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
                         void *stream, dabs_problem **out);
+/*
+ * Load a sparse QUBO matrix in CSR form for the sparse search kernel, which
+ * keeps the deltas of an instance in LDS and on each flip updates only the
+ * deltas of the nonzeros of the flipped row (Eq. (4)): n <= 15,360 bits,
+ * for graphs of bounded degree such as the G-set max-cut instances and the
+ * annealer graph of Section II-C.
+ *   row_ptr_dev [n + 1] int32 (row_ptr[0] = 0, non-decreasing, row_ptr[n] =
+ *   nnz), col_dev [nnz] int32 (strictly increasing within a row), val_dev
+ *   [nnz] int32: the full symmetric matrix, diagonal entries included where
+ *   nonzero.  Off-diagonal weights must lie in [-32767, 32767] (they are
+ *   stored with their column in one 32-bit word); the delta bound B <=
+ *   dabs_max_bound(DABS_W_SPARSE, n).  Validation (ranges, order, symmetry,
+ *   B) runs on the device; the call synchronises `stream`.
+ * Every call that takes a dabs_problem accepts a sparse one, except the
+ * learned proposal's feature calls (DABS_E_UNSUPPORTED).
+ * Errors: DABS_E_INVALID (null, n < 1, nnz < 0, bad row_ptr or column
+ * order), DABS_E_UNSUPPORTED (n > 15,360), DABS_E_NOT_SYMMETRIC,
+ * DABS_E_RANGE, DABS_E_NOMEM, DABS_E_HIP.
+ */
+int dabs_problem_create_csr(const int32_t *row_ptr_dev, const int32_t *col_dev, const int32_t *val_dev,
+                            int32_t n, int64_t nnz, void *stream, dabs_problem **out);
 int dabs_problem_destroy(dabs_problem *p);
 /* n, weight type and delta bound B of a loaded problem (any pointer may be NULL). */
 int dabs_problem_info(const dabs_problem *p, int32_t *n, int32_t *wtype, int64_t *bound);
@@ -384,6 +407,19 @@ int dabs_ising_to_qubo(int32_t n, int64_t nedges, const int32_t *edges_dev, cons
  */
 enum { DABS_PROBE_HBM = 0, DABS_PROBE_MALL = 1, DABS_PROBE_L2 = 2, DABS_PROBE_LDS = 3 };
 int dabs_bandwidth_probe(int32_t level, double *out_host);
+
+/*
+ * The same Ising front-end into a sparse problem (dabs_problem_create_csr)
+ * for models on sparse graphs such as an annealer's hardware graph (Section
+ * II-C: 5,627 nodes, 40,279 edges): the QUBO rows hold the edges and the
+ * diagonal only.  edges_dev [nedges][2], J_dev [nedges], h_dev [n] int32 as
+ * above (repeated edges add; a loop or an index out of range is an error);
+ * *offset_host = c.  The rows are assembled on the host (the call
+ * synchronises `stream`).
+ * Errors: as dabs_problem_create_csr, and DABS_E_INVALID for a bad edge.
+ */
+int dabs_problem_create_ising(int32_t n, int64_t nedges, const int32_t *edges_dev, const int32_t *J_dev,
+                              const int32_t *h_dev, void *stream, dabs_problem **out, int64_t *offset_host);
 
 /*
  * Learned proposal.  Not in the paper: a small network that scores every bit

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdabs.so")
 
 DABS_OK, DABS_E_INVALID, DABS_E_NOT_SYMMETRIC, DABS_E_RANGE, DABS_E_NOMEM, DABS_E_HIP, DABS_E_UNSUPPORTED, \
     DABS_E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
-DABS_W_I16, DABS_W_I32 = 0, 1
+DABS_W_I16, DABS_W_I32, DABS_W_SPARSE = 0, 1, 2
 (DABS_GREEDY, DABS_STRAIGHT, DABS_MAXMIN, DABS_CYCLICMIN, DABS_RANDOMMIN, DABS_POSITIVEMIN,
  DABS_TWONEIGHBOR, DABS_TABU_GREEDY) = range(8)
 (DABS_OP_RANDOM, DABS_OP_BEST, DABS_OP_MUTATION, DABS_OP_CROSSOVER, DABS_OP_XROSSOVER, DABS_OP_ZERO,
@@ -70,6 +70,9 @@ _SIGS = {
     "dabs_batched_set_cancel": ([_P, _P], C.c_int),
     "dabs_problem_create": ([_P, C.c_int32, C.c_int64, C.c_int32, _P, C.POINTER(_P)], C.c_int),
     "dabs_problem_destroy": ([_P], C.c_int),
+    "dabs_problem_create_csr": ([_P, _P, _P, C.c_int32, C.c_int64, _P, C.POINTER(_P)], C.c_int),
+    "dabs_problem_create_ising": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.POINTER(_P), C.POINTER(C.c_int64)],
+                                  C.c_int),
     "dabs_problem_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
     "dabs_energy": ([_P, _P, C.c_int32, _P, _P], C.c_int),
     "dabs_search": ([_P, C.POINTER(dabs_search_params), C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_int32, _P, _P],
@@ -217,9 +220,34 @@ def dabs_problem_create(W, stream=None) -> Problem:
         raise ValueError("W must be int16 or int32")
     h = C.c_void_p()
     _check(lib().dabs_problem_create(_ptr(W), W.shape[0], W.stride(0), wtype, _stream(stream), C.byref(h)))
+    return _problem(h)
+
+
+def _problem(h) -> Problem:
     n, wt, b = C.c_int32(), C.c_int32(), C.c_int64()
     _check(lib().dabs_problem_info(h, C.byref(n), C.byref(wt), C.byref(b)))
     return Problem(h, n.value, wt.value, b.value)
+
+
+def dabs_problem_create_csr(row_ptr, col, val, n: int, stream=None) -> Problem:
+    """A sparse problem from CSR rows (int32 CUDA tensors, the full symmetric
+    matrix with its diagonal entries)."""
+    h = C.c_void_p()
+    nnz = int(col.shape[0])
+    _check(lib().dabs_problem_create_csr(_ptr(row_ptr), _ptr(col) if nnz else None, _ptr(val) if nnz else None,
+                                         n, nnz, _stream(stream), C.byref(h)))
+    return _problem(h)
+
+
+def dabs_problem_create_ising(n: int, edges, J, h, stream=None):
+    """(sparse problem, c) for the Ising model (edges [E][2], J [E], h [n]
+    int32 CUDA tensors): E(X) = H(S) + c."""
+    hd = C.c_void_p()
+    off = C.c_int64()
+    ne = 0 if edges is None else int(edges.shape[0])
+    _check(lib().dabs_problem_create_ising(n, ne, _ptr(edges) if ne else None, _ptr(J) if ne else None, _ptr(h),
+                                           _stream(stream), C.byref(hd), C.byref(off)))
+    return _problem(hd), int(off.value)
 
 
 def dabs_problem_destroy(p: Problem):

@@ -482,8 +482,9 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         for (int i = 0; i < params[p].n_ops; ++i)
             if (params[p].ops[i] == DABS_OP_MLP_SEED || params[p].ops[i] == DABS_OP_MLP_MUTATE) s->mlp_ops = true;
         d.pool_bit0 = pbits;
-        d.W = pr->W; d.diag = pr->diag; d.ld = pr->ld; d.n = pr->n; d.nw = (pr->n + 63) / 64;
-        d.wtype = pr->wtype; d.slots = walk_slots(pr->wtype, pr->n);
+        d.W = pr->W; d.rowptr = pr->rowptr; d.nz = pr->nz;
+        d.diag = pr->diag; d.ld = pr->ld; d.n = pr->n; d.nw = (pr->n + 63) / 64;
+        d.wtype = pr->wtype; d.slots = pr->slots;
         d.instances = instances[p]; d.inst0 = (int32_t)inst;
         d.g = params[p];
         d.pool_cell0 = cells; d.pool_word0 = pwords; d.inst_word0 = iwords;
@@ -884,7 +885,8 @@ int dabs_batched_set_mlp(dabs_batched *s, const dabs_mlp *m) {
         int64_t cnt = 0, feat = 0, bits = 0;
         for (int p = 0; p < s->nprob; ++p) {
             const ProbDesc &d = s->hdesc[p];
-            if (d.n > 4096) return dabs_fail(DABS_E_UNSUPPORTED, "the learned proposal needs n <= 4096");
+            if (d.n > 4096 || d.wtype == DABS_W_SPARSE)
+                return dabs_fail(DABS_E_UNSUPPORTED, "the learned proposal needs a dense W with n <= 4096");
             const int64_t pc = (int64_t)d.g.npools * d.g.capacity;
             cnt = std::max<int64_t>(cnt, (int64_t)d.g.npools * d.n);
             feat = std::max<int64_t>(feat, pc * d.n * 8);

@@ -170,8 +170,10 @@ const char *dabs_last_error(void) { return g_err; }
 int32_t dabs_max_n(int32_t wtype) { return dabs::max_n(wtype); }
 
 int64_t dabs_max_bound(int32_t wtype, int32_t n) {
-    if ((wtype != DABS_W_I16 && wtype != DABS_W_I32) || n < 1 || n > dabs::max_n(wtype)) return -1;
-    return ((int64_t)1 << (29 - key_shift(wtype, walk_slots(wtype, n)))) - 2;
+    if ((wtype != DABS_W_I16 && wtype != DABS_W_I32 && wtype != DABS_W_SPARSE) || n < 1 || n > dabs::max_n(wtype))
+        return -1;
+    const int slots = wtype == DABS_W_SPARSE ? sparse_slots(n) : walk_slots(wtype, n);
+    return ((int64_t)1 << (29 - key_shift(wtype, slots))) - 2;
 }
 
 int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype, void *stream,
@@ -254,6 +256,10 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     p->diag = diag;
     p->rowabs = (int64_t *)rowb;
     p->device = dev;
+    p->rowptr = nullptr;
+    p->nz = nullptr;
+    p->nnz = 0;
+    p->slots = walk_slots(wtype, n);
     *out = p;
     return DABS_OK;
 }
@@ -263,6 +269,8 @@ int dabs_problem_destroy(dabs_problem *p) {
     (void)hipFree(p->W);
     (void)hipFree(p->diag);
     (void)hipFree(p->rowabs);
+    (void)hipFree(p->rowptr);
+    (void)hipFree(p->nz);
     delete p;
     return DABS_OK;
 }
@@ -280,6 +288,10 @@ int dabs_energy(const dabs_problem *p, const uint64_t *x_dev, int32_t count, int
         return dabs_fail(DABS_E_INVALID, "bad energy arguments");
     if (count == 0) return DABS_OK;
     hipStream_t st = (hipStream_t)stream;
+    if (p->wtype == DABS_W_SPARSE) {
+        HIP_OK(sparse_energy(p, x_dev, count, e_dev, st));
+        return DABS_OK;
+    }
     const int nw = (p->n + 63) / 64;
     const int blocks = (count + 3) / 4;
     if (p->wtype == DABS_W_I16)
@@ -330,7 +342,7 @@ int dabs_search(const dabs_problem *p, const dabs_search_params *sp, int32_t cou
     if (trace_dev && trace_cap < 1) return dabs_fail(DABS_E_INVALID, "trace_cap must be >= 1");
     WalkArgs a;
     memset(&a, 0, sizeof(a));
-    a.W = p->W; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
+    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
     a.batch = 0; a.rule = sp->rule; a.T = sp->T; a.tau = sp->tau; a.greedy_cap = sp->greedy_cap;
     a.seed = sp->seed; a.phase = sp->phase; a.inst0 = sp->inst0;
     a.x = x_dev; a.target = target_dev; a.best = best_dev; a.best_e = best_e_dev; a.e = e_dev;
@@ -351,7 +363,7 @@ int dabs_batch_search(const dabs_problem *p, const dabs_batch_params *bp, int32_
     if (bp->tau < 0 || bp->tau > TAU_MAX) return dabs_fail(DABS_E_INVALID, "tau must be in [0, %d]", TAU_MAX);
     WalkArgs a;
     memset(&a, 0, sizeof(a));
-    a.W = p->W; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
+    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
     a.batch = 1; a.T = bp->T; a.Bn = bp->Bn; a.tau = bp->tau; a.greedy_cap = bp->greedy_cap;
     a.seed = bp->seed; a.inst0 = bp->inst0;
     a.algo = algo_dev; a.phase_arr = phase_dev;

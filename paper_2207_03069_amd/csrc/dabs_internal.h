@@ -8,13 +8,19 @@
 
 struct dabs_problem {
     int32_t n;
-    int32_t wtype;       // dabs_wtype
+    int32_t wtype;       // dabs_wtype (DABS_W_SPARSE: CSR rows below instead of W)
     int64_t ld;          // padded row stride (elements), multiple of 512
     int64_t bound;       // max_k |W_kk| + 2 sum_{j!=k} |W_kj|
     void *W;             // device, n rows x ld, zero diagonal, zero padding
     int32_t *diag;       // device, n
     int64_t *rowabs;     // device, n: R_k = |W_kk| + 2 sum_{j != k} |W_kj|
     int device;
+    // sparse problems: off-diagonal rows, each nonzero one word (column in the
+    // low 16 bits, weight in the high 16), and the walker's pieces per lane
+    int32_t *rowptr;     // device, n + 1
+    uint32_t *nz;        // device, nnz off the diagonal
+    int64_t nnz;
+    int32_t slots;
 };
 
 namespace dabs {
@@ -22,6 +28,9 @@ namespace dabs {
 // Kernel arguments of the per-wave search kernels.
 struct WalkArgs {
     const void *W;
+    const int32_t *rowptr;       // sparse problems
+    const uint32_t *nz;
+    int32_t slots;
     const int32_t *diag;
     int64_t ld;
     int32_t n, nwords, count;
@@ -52,7 +61,7 @@ hipError_t launch_walk(const dabs_problem *p, const WalkArgs &a, hipStream_t str
 int walk_slots(int wtype, int n);
 // Shift K of the walker's key words (delta 2^K + local index) for a weight
 // type and slot count: valid keys stay in (-2^29, 2^29) while |delta| <=
-// 2^(29-K) - 2.
+// 2^(29-K) - 2.  (The sparse walker holds four keys per piece, like int32.)
 inline int key_shift(int wtype, int slots) {
     const int v = wtype == DABS_W_I16 ? 8 : 4, logv = wtype == DABS_W_I16 ? 3 : 2;
     int k = 0;
@@ -68,6 +77,8 @@ inline int key_shift(int wtype, int slots) {
 // (q * m + r) * nw).
 struct ProbDesc {
     const void *W;
+    const int32_t *rowptr;         // sparse problems (wtype DABS_W_SPARSE)
+    const uint32_t *nz;
     const int32_t *diag;
     int64_t ld;
     int32_t n, nw, wtype, slots;
@@ -110,6 +121,14 @@ struct ItemsArgs {
 // wave at 128 VGPRs (4 waves per SIMD), 1 leaves the register file uncapped.
 constexpr int WALK_VARIANTS = 2;
 hipError_t launch_walk_items(int wtype, int slots, int variant, const ItemsArgs &a, hipStream_t stream);
+// The sparse walker's item kernel (dabs_sparse.hip), one launch per piece count.
+hipError_t launch_sparse_items(int slots, const ItemsArgs &a, hipStream_t stream);
+// The sparse walker for dabs_search / dabs_batch_search.
+hipError_t launch_sparse_walk(const dabs_problem *p, const WalkArgs &a, hipStream_t stream);
+// E(X) of `count` packed vectors on a sparse problem (dabs_sparse.hip).
+hipError_t sparse_energy(const dabs_problem *p, const uint64_t *x, int count, int64_t *e, hipStream_t st);
+// Pieces per lane of the sparse walker for n bits.
+inline int sparse_slots(int n) { return (n + 255) / 256; }
 // Largest n the walker kernels support for a weight type.
 int max_n(int wtype);
 

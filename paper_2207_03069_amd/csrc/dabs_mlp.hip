@@ -508,7 +508,8 @@ int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev,
                            uint16_t *feat_dev, void *stream) {
     if (!p || !pool_bits_dev || !feat_dev) return dabs_fail(DABS_E_INVALID, "null argument");
     if (npools < 1 || capacity < 1) return dabs_fail(DABS_E_INVALID, "bad pool shape");
-    if (p->n > 4096) return dabs_fail(DABS_E_UNSUPPORTED, "features need n <= 4096");
+    if (p->n > 4096 || p->wtype == DABS_W_SPARSE)
+        return dabs_fail(DABS_E_UNSUPPORTED, "features need a dense W with n <= 4096");
     int *cnt = nullptr;
     HIP_OK(hipMalloc((void **)&cnt, sizeof(int) * (size_t)npools * p->n));
     int r = mlp_pool_logits(p, nullptr, pool_bits_dev, npools, capacity, cnt, (short *)feat_dev, nullptr,
@@ -558,7 +559,8 @@ int dabs_mlp_pool_features_noalloc(const dabs_problem *p, const uint64_t *pool_b
                                    int32_t capacity, uint16_t *feat_dev, void *stream) {
     if (!p || !pool_bits_dev || !feat_dev) return dabs_fail(DABS_E_INVALID, "null argument");
     if (npools < 1 || capacity < 1) return dabs_fail(DABS_E_INVALID, "bad pool shape");
-    if (p->n > 4096) return dabs_fail(DABS_E_UNSUPPORTED, "features need n <= 4096");
+    if (p->n > 4096 || p->wtype == DABS_W_SPARSE)
+        return dabs_fail(DABS_E_UNSUPPORTED, "features need a dense W with n <= 4096");
     if ((int64_t)npools * p->n > DABS_NOALLOC_COUNTS)
         return dabs_fail(DABS_E_INVALID, "npools * n = %lld above the %d counts of the static buffer",
                          (long long)npools * p->n, DABS_NOALLOC_COUNTS);

@@ -3,6 +3,7 @@
 // and slot count (slots = ceil(n / (64 * 16 / sizeof(weight)))).
 #include "dabs_internal.h"
 #include "dabs_walker.h"
+#include "dabs_sparse.h"
 
 namespace dabs {
 
@@ -113,6 +114,7 @@ int walk_slots(int wtype, int n) {
 
 hipError_t launch_walk_items(int wtype, int slots, int variant, const ItemsArgs &a, hipStream_t st) {
     if (variant < 0 || variant >= WALK_VARIANTS) return hipErrorInvalidValue;
+    if (wtype == DABS_W_SPARSE) return launch_sparse_items(slots, a, st);
     if (wtype == DABS_W_I16) {
         switch (slots) {
         case 1: return go_items<int16_t, 1>(variant, a, st);
@@ -138,9 +140,13 @@ static hipError_t go(const WalkArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-int max_n(int wtype) { return wtype == DABS_W_I16 ? 8 * 512 : 8 * 256; }
+int max_n(int wtype) {
+    if (wtype == DABS_W_SPARSE) return SPARSE_MAX_SLOTS * 256;
+    return wtype == DABS_W_I16 ? 8 * 512 : 8 * 256;
+}
 
 hipError_t launch_walk(const dabs_problem *p, const WalkArgs &a, hipStream_t st) {
+    if (p->wtype == DABS_W_SPARSE) return launch_sparse_walk(p, a, st);
     const int slots = walk_slots(p->wtype, p->n);
     if (p->wtype == DABS_W_I16) {
         switch (slots) {

@@ -187,6 +187,16 @@ def ising_instance(n: int, edges: np.ndarray, r: int, seed: int):
     return J, h
 
 
+def csr_from_dense(W: np.ndarray):
+    """CSR rows (row_ptr, col, val as int32) of the nonzeros of W, columns
+    increasing within a row."""
+    W = np.asarray(W)
+    rows, cols = np.nonzero(W)
+    rp = np.zeros(W.shape[0] + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp).astype(np.int32), cols.astype(np.int32), W[rows, cols].astype(np.int32)
+
+
 def batched_sizes(count: int = 256, lo: int = 256, ratio: int = 16, seed: int = 0) -> np.ndarray:
     """Problem sizes n = floor(lo * ratio^U), U ~ U[0,1), for the many-problem
     workload (log-uniform in [256, 4096))."""

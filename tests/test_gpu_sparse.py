@@ -1,0 +1,247 @@
+"""GPU parity of the sparse search kernel (deltas in LDS, each flip updating
+only the nonzeros of the flipped row) against the CPU oracle, which runs on
+the same matrix stored dense: energies, every search rule, the batch search
+and the generational loop bit for bit; CSR validation; the Ising front-end
+into a sparse problem on an annealer-shaped graph (Section II-C: 5,627
+nodes, 40,279 edges, degree <= 15) of resolution 1, 16 and 256."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_03069_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2207_03069_amd as dabs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+CAP = 100000
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def sparse_problem(W):
+    rp, col, val = inputs.csr_from_dense(W)
+    return dabs.dabs_problem_create_csr(dev(rp), dev(col), dev(val), W.shape[0])
+
+
+def random_sparse(n, p, lo, hi, seed):
+    """Symmetric W on G(n, p) with weights uniform nonzero in [lo, hi] and a
+    diagonal uniform in [4 lo, 4 hi]."""
+    edges, _ = inputs.maxcut_graph(n, p, seed)
+    rng = np.random.default_rng(seed + 7)
+    w = rng.integers(lo, hi + 1, size=len(edges))
+    w[w == 0] = 1
+    W = np.zeros((n, n), np.int64)
+    W[edges[:, 0], edges[:, 1]] = w
+    W[edges[:, 1], edges[:, 0]] = w
+    np.fill_diagonal(W, rng.integers(4 * lo, 4 * hi + 1, size=n))
+    return W
+
+
+CASES = [(1, 0.0, "rand"), (24, 0.3, "rand"), (300, 0.05, "rand"), (257, 0.1, "maxcut"),
+         (800, 0.06, "maxcut"), (2000, 0.01, "rand")]
+
+
+def case_W(n, p, kind):
+    if kind == "maxcut":
+        W, _, _ = inputs.maxcut_instance(n, p, seed=n, dtype=np.int64)
+        return W
+    return random_sparse(n, p, -50, 50, n)
+
+
+@pytest.mark.parametrize("n,p,kind", CASES + [(5000, 0.002, "rand")])
+def test_sparse_energy_parity(n, p, kind):
+    W = case_W(n, p, kind)
+    pr = sparse_problem(W)
+    X = inputs.random_bits(9, n, n + 3)
+    X[0] = 0
+    X[1] = 1
+    e = torch.zeros(9, dtype=torch.int64, device=DEV)
+    dabs.dabs_energy(pr, dev(inputs.pack_bits(X).view(np.int64)), e)
+    got = e.cpu().numpy()
+    for c in range(9):
+        assert got[c] == oracle.energy(W, X[c])
+
+
+RULES = [oracle.GREEDY, oracle.STRAIGHT, oracle.MAXMIN, oracle.CYCLICMIN, oracle.RANDOMMIN,
+         oracle.POSITIVEMIN, oracle.TWONEIGHBOR, oracle.TABU_GREEDY]
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("n,p,kind", CASES)
+def test_sparse_search_parity(rule, n, p, kind):
+    W = case_W(n, p, kind)
+    print("sparse search n=%d %s rule %d" % (n, kind, rule), flush=True)
+    pr = sparse_problem(W)
+    cnt = 4
+    X0 = inputs.random_bits(cnt, n, 11 + n)
+    targets = inputs.random_bits(cnt, n, 12 + n)
+    T = max(1, min(300, 2 * n))
+    cap = 2 * n + 300
+    x = dev(inputs.pack_bits(X0).view(np.int64))
+    best = torch.zeros_like(x)
+    be = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    e = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    delta = torch.zeros((cnt, n), dtype=torch.int32, device=DEV)
+    trace = torch.zeros((cnt, cap), dtype=torch.int32, device=DEV)
+    flips = torch.zeros(cnt, dtype=torch.int32, device=DEV)
+    sp = dabs.dabs_search_params(rule=rule, T=T, tau=5, greedy_cap=CAP, seed=3, phase=1, inst0=2)
+    dabs.dabs_search(pr, sp, x, dev(inputs.pack_bits(targets).view(np.int64)), best, be, e, delta, trace, flips)
+    torch.cuda.synchronize()
+    gx = inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n)
+    gb = inputs.unpack_bits(best.cpu().numpy().view(np.uint64), n)
+    for c in range(cnt):
+        r = oracle.search(W, rule, X0[c], T=T, tau=5, seed=3, inst=2 + c, ph=1, target=targets[c], greedy_cap=CAP,
+                          trace_cap=cap)
+        f = r["flips"]
+        assert int(flips[c]) == f, c
+        assert np.array_equal(trace[c].cpu().numpy()[:min(f, cap)], r["trace"][:min(f, cap)]), c
+        assert int(e[c]) == r["e"] and int(be[c]) == r["ebest"], c
+        assert np.array_equal(gx[c], r["x"]) and np.array_equal(gb[c], r["best"]), c
+        assert np.array_equal(delta[c].cpu().numpy().astype(np.int64), r["delta"]), c
+
+
+@pytest.mark.parametrize("n,p,kind", [(300, 0.05, "rand"), (800, 0.06, "maxcut")])
+def test_sparse_batch_search_parity(n, p, kind):
+    W = case_W(n, p, kind)
+    pr = sparse_problem(W)
+    algos = np.array([oracle.MAXMIN, oracle.CYCLICMIN, oracle.RANDOMMIN, oracle.POSITIVEMIN, oracle.TWONEIGHBOR] * 2,
+                     np.int32)
+    cnt = len(algos)
+    X0 = inputs.random_bits(cnt, n, 5)
+    D = inputs.random_bits(cnt, n, 6)
+    T, Bn = max(1, n // 10), 2 * n
+    x = dev(inputs.pack_bits(X0).view(np.int64))
+    ph = torch.arange(cnt, dtype=torch.int32, device=DEV)
+    best = torch.zeros_like(x)
+    be = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    e = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    fl = torch.zeros(cnt, dtype=torch.int32, device=DEV)
+    bp = dabs.dabs_batch_params(T=T, Bn=Bn, tau=8, greedy_cap=CAP, seed=9, inst0=0)
+    dabs.dabs_batch_search(pr, bp, x, dev(inputs.pack_bits(D).view(np.int64)), dev(algos), ph, best, be, e, fl)
+    torch.cuda.synchronize()
+    gx = inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n)
+    gb = inputs.unpack_bits(best.cpu().numpy().view(np.uint64), n)
+    for c in range(cnt):
+        r = oracle.batch_search(W, int(algos[c]), X0[c], D[c], T=T, Bn=Bn, tau=8, seed=9, inst=c, ph=c,
+                                greedy_cap=CAP)
+        assert int(fl[c]) == r["flips"] and int(ph[c]) == r["ph"], c
+        assert int(e[c]) == r["e"] and int(be[c]) == r["ebest"], c
+        assert np.array_equal(gx[c], r["x"]) and np.array_equal(gb[c], r["best"]), c
+
+
+def pools_of(getter, n, P, m):
+    nw = (n + 63) // 64
+    bits = torch.zeros((P, m, nw), dtype=torch.int64, device=DEV)
+    pe = torch.zeros((P, m), dtype=torch.int64, device=DEV)
+    getter(bits, pe)
+    torch.cuda.synchronize()
+    return inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), pe.cpu().numpy()
+
+
+def test_sparse_solver_parity_maxcut():
+    """G(800, 0.06) max-cut as a sparse problem: generational rounds bit-exact."""
+    W, _, _ = inputs.maxcut_instance(800, 0.06, seed=2, dtype=np.int64)
+    pr = sparse_problem(W)
+    kw = dict(T=80, Bn=1600, tau=8, seed=1, capacity=10, npools=2, greedy_cap=CAP)
+    inst, rounds = 24, 3
+    s = dabs.dabs_solver_create(pr, dabs.ga_params(**kw), inst)
+    dabs.dabs_solver_run(s, rounds)
+    bits, pe = pools_of(lambda b, e: dabs.dabs_solver_pools(s, b, e), 800, 2, 10)
+    ref = oracle.solve(W, oracle.ga_params(**kw), inst, rounds)
+    assert np.array_equal(pe, ref["pool_e"]) and np.array_equal(bits, ref["pool_bits"])
+
+
+def test_batched_dense_and_sparse_problems():
+    """One batch holding dense int16, dense int32 and sparse problems: every
+    problem evolves as the oracle's loop on it alone."""
+    Ws = [inputs.dense_qubo(200, -100, 100, 1), random_sparse(700, 0.02, -30, 30, 2),
+          inputs.dense_qubo(90, -1000, 1000, 3, dtype=np.int32), random_sparse(3000, 0.002, -9, 9, 4)]
+    probs = [dabs.dabs_problem_create(dev(Ws[0])), sparse_problem(Ws[1]), dabs.dabs_problem_create(dev(Ws[2])),
+             sparse_problem(Ws[3])]
+    params, inst = [], [8, 12, 6, 4]
+    for k, W in enumerate(Ws):
+        n = W.shape[0]
+        params.append(dict(T=max(1, n // 10), Bn=n, tau=6, seed=10 + k, capacity=6, npools=2, greedy_cap=CAP))
+    b = dabs.dabs_batched_create(probs, [dabs.ga_params(**g) for g in params], inst)
+    dabs.dabs_batched_run(b, 2, None, use_graph=True)
+    for k, W in enumerate(Ws):
+        n = W.shape[0]
+        bits, pe = pools_of(lambda bb, e: dabs.dabs_batched_pools(b, k, bb, e), n, 2, 6)
+        ref = oracle.solve(W, oracle.ga_params(**params[k]), inst[k], 2)
+        assert np.array_equal(pe, ref["pool_e"]), k
+        assert np.array_equal(bits, ref["pool_bits"]), k
+
+
+def test_csr_validation_errors():
+    W = random_sparse(100, 0.1, -5, 5, 1)
+    rp, col, val = inputs.csr_from_dense(W)
+
+    def load(rp, col, val, n=100):
+        return dabs.dabs_problem_create_csr(dev(rp), dev(col), dev(val), n)
+
+    def status(*a, **k):
+        with pytest.raises(dabs.DabsError) as e:
+            load(*a, **k)
+        return e.value.status
+    load(rp, col, val)
+    v2 = val.copy()
+    k = int(np.nonzero(col[rp[3]:rp[4]] != 3)[0][0]) + rp[3]
+    v2[k] += 1                                                       # (3, j) != (j, 3)
+    assert status(rp, col, v2) == dabs.DABS_E_NOT_SYMMETRIC
+    c2 = col.copy()
+    c2[rp[5]], c2[rp[5] + 1] = c2[rp[5] + 1], c2[rp[5]]              # columns out of order
+    assert status(rp, c2, val) == dabs.DABS_E_INVALID
+    r2 = rp.copy()
+    r2[-1] -= 1
+    assert status(r2, col, val) == dabs.DABS_E_INVALID
+    W3 = W.copy()
+    W3[1, 2] = W3[2, 1] = 40000                                      # does not fit the packed weight
+    assert status(*inputs.csr_from_dense(W3)) == dabs.DABS_E_RANGE
+    W4 = W.copy()
+    W4[0, 0] = dabs.dabs_max_bound(dabs.DABS_W_SPARSE, 100)          # B above the bound
+    assert status(*inputs.csr_from_dense(W4)) == dabs.DABS_E_RANGE
+    with pytest.raises(dabs.DabsError) as e:
+        dabs.dabs_problem_create_csr(dev(np.zeros(20001, np.int32)), dev(np.zeros(0, np.int32)),
+                                     dev(np.zeros(0, np.int32)), 20000)
+    assert e.value.status == dabs.DABS_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("r", [1, 16, 256])
+def test_ising_annealer_graph_sparse(r):
+    """An Ising model of resolution r on a 5,627-node, 40,279-edge graph of
+    degree <= 15 (the shape of Section II-C) loaded as a sparse problem: c
+    and the energies against the Hamiltonian, and two MaxMin / RandomMin
+    instances bit-exact with the oracle on the dense QUBO."""
+    n, m = 5627, 40279
+    edges = inputs.sparse_graph(n, m, 15, 0)
+    J, h = inputs.ising_instance(n, edges, r, r)
+    pr, c = dabs.dabs_problem_create_ising(n, dev(edges.astype(np.int32)), dev(J.astype(np.int32)),
+                                           dev(h.astype(np.int32)))
+    W, cref, _ = oracle.ising_qubo(n, edges, J, h)
+    assert c == cref
+    X = inputs.random_bits(3, n, r)
+    e = torch.zeros(3, dtype=torch.int64, device=DEV)
+    dabs.dabs_energy(pr, dev(inputs.pack_bits(X).view(np.int64)), e)
+    for k in range(3):
+        assert int(e[k]) == oracle.ising_hamiltonian(edges, J, h, 2 * X[k].astype(np.int64) - 1) + c
+    for rule in (oracle.MAXMIN, oracle.RANDOMMIN):
+        x = dev(inputs.pack_bits(X[:2]).view(np.int64))
+        best = torch.zeros_like(x)
+        be = torch.zeros(2, dtype=torch.int64, device=DEV)
+        ee = torch.zeros(2, dtype=torch.int64, device=DEV)
+        trace = torch.zeros((2, 200), dtype=torch.int32, device=DEV)
+        sp = dabs.dabs_search_params(rule=rule, T=200, tau=8, greedy_cap=CAP, seed=r, phase=0, inst0=0)
+        dabs.dabs_search(pr, sp, x, None, best, be, ee, None, trace, None)
+        torch.cuda.synchronize()
+        for k in range(2):
+            ref = oracle.search(W, rule, X[k], T=200, tau=8, seed=r, inst=k, ph=0, greedy_cap=CAP, trace_cap=200)
+            assert np.array_equal(trace[k].cpu().numpy(), ref["trace"]), (rule, k)
+            assert int(ee[k]) == ref["e"] and int(be[k]) == ref["ebest"], (rule, k)
