@@ -473,7 +473,8 @@ def main():
                         "unit": "Tops/s (int32 lane-ops: 2n per flip, Eq. (4) update + Steps 1-2 comparison)",
                         "frac": achieved_ops / VALU_PEAK_OPS},
                 "autotune": {"variant_ms": tune_ms[0], "chosen": tune_choice[0],
-                             "variants": ["<=128 VGPRs (4 waves/SIMD)", "uncapped registers"]}}
+                             "variants": ["<=128 VGPRs (4 waves/SIMD)", "uncapped registers",
+                                          "W in LDS (-1: does not fit)"]}}
 
     tts = None
     target_e = best_e

@@ -359,15 +359,21 @@ int dabs_batched_set_cancel(dabs_batched *b, const volatile int32_t *flag_host);
 
 /*
  * Autotuner: for every size class of the batch (weight type x slot count),
- * times each compiled variant of the batch-search kernel (register cap for
- * 4 waves per SIMD, or uncapped) on the batch's own next-round items and keeps
- * the fastest for the following rounds.  The instance state is saved and
- * restored, so results are unchanged (only speed).  Synchronises the stream.
- *   ms_out     nullable [nclasses][2] milliseconds per variant
+ * times each compiled variant of the batch-search kernel on the batch's own
+ * next-round items and keeps the fastest for the following rounds:
+ *   0  W rows from global memory / L2, registers capped for 4 waves per SIMD,
+ *   1  the same with the register file uncapped,
+ *   2  W staged in LDS, one copy per workgroup of four waves (classes of one
+ *      slot whose every W fits in 40 KB; -1 ms for other classes).
+ * The instance state is saved and restored, so results are unchanged (only
+ * speed).  Sparse classes have one kernel (every variant runs it).
+ * Synchronises the stream.
+ *   ms_out     nullable [nclasses][DABS_WALK_VARIANTS] milliseconds per variant
  *   choice_out nullable [nclasses] chosen variant
  * dabs_batched_classes fills [min(nclasses, cap)][4] = (wtype, slots, items,
  * variant) and returns nclasses.
  */
+#define DABS_WALK_VARIANTS 3
 int dabs_batched_autotune(dabs_batched *b, double *ms_out, int32_t *choice_out, void *stream);
 int dabs_solver_autotune(dabs_solver *s, double *ms_out, int32_t *choice_out, void *stream);
 int dabs_batched_classes(const dabs_batched *b, int32_t *wtype_slots_count_variant, int32_t cap);

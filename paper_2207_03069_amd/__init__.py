@@ -53,6 +53,7 @@ class dabs_ga_params(C.Structure):
 
 DABS_SOLVER_TIME_WALK = 1
 DABS_GA_RESTART = 2
+DABS_WALK_VARIANTS = 3
 
 
 # every function the header declares: name -> (argtypes, restype)
@@ -505,17 +506,38 @@ def dabs_batched_classes(b: Batched):
     return [tuple(out[4 * c:4 * c + 4]) for c in range(nc)]
 
 
+def walk_slots(wtype: int, n: int) -> int:
+    """Slots (16-byte pieces per lane, a power of two) of the dense walker."""
+    span = 512 if wtype == DABS_W_I16 else 256
+    s = 1
+    while s * span < n:
+        s *= 2
+    return s
+
+
+def lds_w_bytes(wtype: int, n: int) -> int:
+    """Bytes of the LDS copy of a dense W of one slot (rows rounded up to a
+    16-byte piece), 0 when the problem cannot use it (more than 40 KB)."""
+    v, es = (8, 2) if wtype == DABS_W_I16 else (4, 4)
+    if wtype not in (DABS_W_I16, DABS_W_I32) or n > 64 * v:
+        return 0
+    b = n * ((n + v - 1) // v * v) * es
+    return b if b <= 40960 else 0
+
+
 def dabs_batched_autotune(b: Batched, stream=None):
     """Returns (milliseconds [class][variant], chosen variant per class)."""
     nc = len(dabs_batched_classes(b))
-    ms = (C.c_double * (2 * nc))()
+    V = DABS_WALK_VARIANTS
+    ms = (C.c_double * (V * nc))()
     ch = (C.c_int32 * nc)()
     _check(lib().dabs_batched_autotune(b.handle, C.cast(ms, C.c_void_p), C.cast(ch, C.c_void_p), _stream(stream)))
-    return [[ms[2 * c], ms[2 * c + 1]] for c in range(nc)], list(ch)
+    return [[ms[V * c + v] for v in range(V)] for c in range(nc)], list(ch)
 
 
 def dabs_solver_autotune(s: Solver, stream=None):
-    ms = (C.c_double * 2)()
+    V = DABS_WALK_VARIANTS
+    ms = (C.c_double * V)()
     ch = (C.c_int32 * 1)()
     _check(lib().dabs_solver_autotune(s.handle, C.cast(ms, C.c_void_p), C.cast(ch, C.c_void_p), _stream(stream)))
-    return [[ms[0], ms[1]]], list(ch)
+    return [[ms[v] for v in range(V)]], list(ch)

@@ -403,7 +403,7 @@ struct dabs_batched {
     int *item0;                        // device, first item of each problem
     int2 *pool_list;                   // device, (problem, pool)
     int npool_list;
-    struct Cls { int wtype, slots, begin, count, variant; };
+    struct Cls { int wtype, slots, begin, count, variant, lds_bytes; };
     std::vector<Cls> classes;
     hipStream_t side[MAX_CLASSES];
     hipEvent_t fork, join[MAX_CLASSES];
@@ -515,11 +515,23 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
             const ProbDesc &A = s->hdesc[a], &B = s->hdesc[b];
             return (int64_t)A.n * (A.g.Bn + A.n) > (int64_t)B.n * (B.g.Bn + B.n);
         });
-        // default variant until tuned: measured faster uncapped from 4 slots up
-        dabs_batched::Cls c = {k.first, k.second, (int)items.size(), 0, k.second >= 4 ? 1 : 0};
+        // W in LDS (variant 2) when every W of the class fits; the class's
+        // items are then laid out in groups of four of one problem (each
+        // problem padded with dummies of instance -1)
+        int lb = 0;
+        for (int p : ps) {
+            const int b = lds_w_bytes(s->hdesc[p].wtype, s->hdesc[p].n);
+            lb = (b == 0 || lb < 0) ? -1 : std::max(lb, b);
+        }
+        lb = lb < 0 ? 0 : lb;
+        // default variant until tuned: LDS rows where they fit, else measured
+        // faster uncapped from 4 slots up
+        dabs_batched::Cls c = {k.first, k.second, (int)items.size(), 0, lb > 0 ? 2 : (k.second >= 4 ? 1 : 0), lb};
         for (int p : ps) {
             item0[p] = (int)items.size();
             for (int i = 0; i < s->hdesc[p].instances; ++i) items.push_back(make_int2(p, i));
+            if (lb > 0)
+                while (items.size() % 4) items.push_back(make_int2(p, -1));
         }
         c.count = (int)items.size() - c.begin;
         s->classes.push_back(c);
@@ -619,6 +631,7 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
         a.items = s->items + s->classes[c].begin;
         a.nitems = s->classes[c].count;
         a.ttt = ttt;
+        a.lds_bytes = s->classes[c].lds_bytes;
         HIP_OK(launch_walk_items(s->classes[c].wtype, s->classes[c].slots, s->classes[c].variant, a, cs));
         if (nc > 1) HIP_OK(hipEventRecord(s->join[c], cs));
     }
@@ -831,6 +844,10 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
         double best = 1e300;
         int pick = 0;
         for (int v = 0; v < WALK_VARIANTS && status == DABS_OK; ++v) {
+            if (v == 2 && s->classes[c].lds_bytes <= 0) {          // W does not fit in LDS
+                if (ms_out) ms_out[c * WALK_VARIANTS + v] = -1.0;
+                continue;
+            }
             float ms = 0.f;
             for (int rep = 0; rep < 2 && status == DABS_OK; ++rep) {   // the first launch loads the code object
                 copy(s->d.x, sx, xw); copy(s->d.ph, sph, i4);
@@ -839,6 +856,7 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
                 a.items = s->items + s->classes[c].begin;
                 a.nitems = s->classes[c].count;
                 a.ttt = 0;
+                a.lds_bytes = s->classes[c].lds_bytes;
                 if (status == DABS_OK &&
                     (hipEventRecord(e0, st) != hipSuccess ||
                      launch_walk_items(s->classes[c].wtype, s->classes[c].slots, v, a, st) != hipSuccess ||

@@ -116,10 +116,24 @@ struct ItemsArgs {
     const int2 *items;
     int32_t nitems;
     int32_t ttt;                   // record time to target
+    int32_t lds_bytes;             // variant 2: LDS for the largest W of the class
 };
 // Compiled variants of the item kernel per (weight type, slot count): 0 caps a
-// wave at 128 VGPRs (4 waves per SIMD), 1 leaves the register file uncapped.
-constexpr int WALK_VARIANTS = 2;
+// wave at 128 VGPRs (4 waves per SIMD), 1 leaves the register file uncapped,
+// 2 (problems of one slot whose W fits, see lds_w_bytes) stages W in LDS,
+// one copy per workgroup of four waves running four items of one problem.
+constexpr int WALK_VARIANTS = DABS_WALK_VARIANTS;
+constexpr int LDS_W_MAX = 40960;
+// Bytes of the LDS copy of W (rows n rounded up to a 16-byte piece), or 0
+// when the problem cannot use it (more than one slot, larger than LDS_W_MAX,
+// sparse).
+inline int lds_w_bytes(int wtype, int n) {
+    if (wtype != DABS_W_I16 && wtype != DABS_W_I32) return 0;
+    const int v = wtype == DABS_W_I16 ? 8 : 4, es = wtype == DABS_W_I16 ? 2 : 4;
+    if (n > 64 * v) return 0;
+    const long long b = (long long)n * ((n + v - 1) / v * v) * es;
+    return b <= LDS_W_MAX ? (int)b : 0;
+}
 hipError_t launch_walk_items(int wtype, int slots, int variant, const ItemsArgs &a, hipStream_t stream);
 // The sparse walker's item kernel (dabs_sparse.hip), one launch per piece count.
 hipError_t launch_sparse_items(int slots, const ItemsArgs &a, hipStream_t stream);

@@ -99,8 +99,11 @@ __device__ __forceinline__ Sel uniform(Sel s) {
     return s;
 }
 
-template <typename WT, int SLOTS>
+// LDSW: the rows come from a copy of W in the workgroup's LDS (problems of
+// one slot whose W fits, see lds_w_bytes) instead of global memory / L2.
+template <typename WT, int SLOTS, bool LDSW = false>
 struct Walker {
+    static_assert(!LDSW || SLOTS == 1, "LDS rows serve problems of one slot");
     static constexpr int V = 16 / (int)sizeof(WT);
     static constexpr int LOGV = V == 8 ? 3 : 2;
     static constexpr int EPL = V * SLOTS;
@@ -191,12 +194,24 @@ struct Walker {
     }
 
     // Row i of the zero-diagonal copy of W as this lane's 16-byte pieces.  The
-    // padded rows hold zeros, so every lane loads every slot.
+    // padded rows hold zeros, so every lane loads every slot.  From LDS, the
+    // rows are ldl elements long (n rounded up to a 16-byte piece) and a lane
+    // whose piece starts past the row takes zeros.
+    __attribute__((address_space(3))) const WT *Wl;
+    int ldl;
     __device__ __forceinline__ void load_row(int i, uint4 (&q)[SLOTS]) const {
         if ((unsigned)i >= (unsigned)n) i = 0;     // never read outside W (a selection bug shows in parity)
-        const WT *row = W + (int64_t)i * ld + lane * V;
+        if constexpr (LDSW) {
+            typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+            const int off = lane * V;
+            u4 v = {0u, 0u, 0u, 0u};
+            if (off < ldl) v = *(__attribute__((address_space(3))) const u4 *)(Wl + i * ldl + off);
+            q[0] = make_uint4(v[0], v[1], v[2], v[3]);
+        } else {
+            const WT *row = W + (int64_t)i * ld + lane * V;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) q[s] = *(const uint4 *)(row + s * SPAN);
+            for (int s = 0; s < SLOTS; ++s) q[s] = *(const uint4 *)(row + s * SPAN);
+        }
     }
     // kb_k += 2 y_i y_k W_ik 2^KB for all k (y = 1 - 2x) from the loaded row.
     // int16: y_i W is one packed 16-bit multiply per word (the library rejects

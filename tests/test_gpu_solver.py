@@ -137,8 +137,15 @@ def batched_run(problems, params, instances, rounds, use_graph, target=None, aut
     if autotune:
         dabs.dabs_batched_run(b, 1, None, use_graph=use_graph)     # tune on a round with real pools
         ms, choice = dabs.dabs_batched_autotune(b)
-        assert len(ms) == len(dabs.dabs_batched_classes(b)) and all(v in (0, 1) for v in choice)
-        assert all(t > 0 for row in ms for t in row)
+        classes = dabs.dabs_batched_classes(b)
+        assert len(ms) == len(classes) and all(v in (0, 1, 2) for v in choice)
+        for (wtype, slots, _, _), row in zip(classes, ms):
+            assert row[0] > 0 and row[1] > 0
+            # W in LDS is timed exactly for the classes of one slot whose W fit
+            assert (row[2] > 0) == (slots == 1 and all(
+                dabs.lds_w_bytes(wtype, W.shape[0]) > 0 for W in problems
+                if (W.dtype == np.int16) == (wtype == dabs.DABS_W_I16) and
+                dabs.walk_slots(wtype, W.shape[0]) == 1))
         dabs.dabs_batched_run(b, rounds - 1, None, use_graph=use_graph)
     else:
         dabs.dabs_batched_run(b, rounds, tgt_or_none(target), use_graph=use_graph)
