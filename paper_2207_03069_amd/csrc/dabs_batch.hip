@@ -93,6 +93,44 @@ __global__ void k_pool_init(BatchDev b, int p) {
     fill_pools(b, b.desc[p], 0u, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
+// The choices of instance inst in round rd (Section IV-A, IV-B): operation
+// and main algorithm (uniform with probability p_explore, else the column of
+// a uniform entry of its pool), parents by rank selection (the second from
+// the next pool for Xrossover), and the words v of the operation's draws.
+struct GaChoice {
+    int op, algo, q, qb, ra, rb;
+    R4 v;
+};
+__device__ __forceinline__ GaChoice ga_choice(const BatchDev &b, const ProbDesc &d, int inst, uint32_t rd) {
+    const dabs_ga_params &g = d.g;
+    const int m = g.capacity, P = g.npools;
+    GaChoice h;
+    h.q = inst % P;
+    const R4 c = philox(rd, (uint32_t)inst, 0, ((uint32_t)TAG_GA << 24) | KIND_CHOICE, g.seed);
+    h.v = philox(rd, (uint32_t)inst, 1, ((uint32_t)TAG_GA << 24) | KIND_CHOICE, g.seed);
+    const int64_t cell = d.pool_cell0 + (int64_t)h.q * m;
+    h.op = c.w[0] < g.p_explore ? g.ops[scale32(c.w[1], (uint32_t)g.n_ops)]
+                                : b.pool_op[cell + scale32(c.w[1], (uint32_t)m)];
+    h.algo = c.w[2] < g.p_explore ? g.algos[scale32(c.w[3], (uint32_t)g.n_algos)]
+                                  : b.pool_algo[cell + scale32(c.w[3], (uint32_t)m)];
+    h.qb = h.op == DABS_OP_XROSSOVER ? (h.q + 1) % P : h.q;
+    h.ra = (int)rank_index(h.v.w[0], (uint32_t)m);
+    h.rb = (int)rank_index(h.v.w[1], (uint32_t)m);
+    return h;
+}
+
+// Before the pools are scored: flag the pool entries that this round's
+// learned operations take as parents (one thread per global instance), so
+// that only their features are computed.
+__global__ __launch_bounds__(256) void k_ga_need(BatchDev b, int total) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= total) return;
+    const ProbDesc &d = b.desc[b.inst_prob[gi]];
+    const GaChoice h = ga_choice(b, d, gi - d.inst0, (uint32_t)b.ctr[2]);
+    if (h.op == DABS_OP_MLP_SEED || h.op == DABS_OP_MLP_MUTATE)
+        b.need[d.pool_cell0 + (int64_t)h.q * d.g.capacity + h.ra] = 1;
+}
+
 // Target generation (Section IV-A, IV-B): one wave per global instance, lane
 // w builds word w of the target (n <= 4096: at most 64 words).
 __global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
@@ -103,20 +141,14 @@ __global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
     const ProbDesc &d = b.desc[p];
     const dabs_ga_params &g = d.g;
     const int inst = gi - d.inst0;
-    const int m = g.capacity, n = d.n, nw = d.nw, P = g.npools;
-    const int q = inst % P;
+    const int m = g.capacity, n = d.n, nw = d.nw;
     const uint32_t rd = (uint32_t)b.ctr[2];
-    const R4 c = philox(rd, (uint32_t)inst, 0, ((uint32_t)TAG_GA << 24) | KIND_CHOICE, g.seed);
-    const R4 v = philox(rd, (uint32_t)inst, 1, ((uint32_t)TAG_GA << 24) | KIND_CHOICE, g.seed);
-    const int64_t cell = d.pool_cell0 + (int64_t)q * m;
-    const int op = c.w[0] < g.p_explore ? g.ops[scale32(c.w[1], (uint32_t)g.n_ops)]
-                                        : b.pool_op[cell + scale32(c.w[1], (uint32_t)m)];
-    const int algo = c.w[2] < g.p_explore ? g.algos[scale32(c.w[3], (uint32_t)g.n_algos)]
-                                          : b.pool_algo[cell + scale32(c.w[3], (uint32_t)m)];
-    const int qb = op == DABS_OP_XROSSOVER ? (q + 1) % P : q;
+    const GaChoice h = ga_choice(b, d, inst, rd);
+    const int op = h.op, algo = h.algo, q = h.q;
+    const R4 v = h.v;
     const uint64_t *pool = b.pool_bits + d.pool_word0;
-    const uint64_t *pa = pool + ((int64_t)q * m + rank_index(v.w[0], (uint32_t)m)) * nw;
-    const uint64_t *pb = pool + ((int64_t)qb * m + rank_index(v.w[1], (uint32_t)m)) * nw;
+    const uint64_t *pa = pool + ((int64_t)q * m + h.ra) * nw;
+    const uint64_t *pb = pool + ((int64_t)h.qb * m + h.rb) * nw;
     const uint64_t *p0 = pool + (int64_t)q * m * nw;
     uint64_t *out = b.target + d.inst_word0 + (int64_t)inst * nw;
     const uint32_t lo32 = (uint32_t)(n < 32 ? n : 32);
@@ -155,9 +187,8 @@ __global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
         case DABS_OP_MLP_SEED:
         case DABS_OP_MLP_MUTATE:
             // learned operations on parent A, scored by A's logits
-            t = b.pool_logits ? mlp_op_word(op, A, b.pool_logits + d.pool_bit0 +
-                                                       ((int64_t)q * m + rank_index(v.w[0], (uint32_t)m)) * n,
-                                            n, w, g.seed, rd, (uint32_t)inst)
+            t = b.pool_logits ? mlp_op_word(op, A, b.pool_logits + d.pool_bit0 + ((int64_t)q * m + h.ra) * n, n, w,
+                                            g.seed, rd, (uint32_t)inst)
                               : A;
             break;
         case DABS_OP_INTERVALZERO: {
@@ -443,6 +474,7 @@ static void batched_free(dabs_batched *s) {
     (void)hipFree(s->mlp_cnt);
     (void)hipFree(s->mlp_feat);
     (void)hipFree(s->mlp_logits);
+    (void)hipFree(s->d.need);
     delete s;
 }
 
@@ -602,13 +634,18 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
 // One round on stream st: targets, batch searches (one launch per size
 // class; classes run on parallel streams), packet insertion, round++.
 static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturing) {
-    if (s->mlp && s->mlp_ops)         // pools are scored only when an MLP operation can be chosen
+    if (s->mlp && s->mlp_ops) {       // pools are scored only when an MLP operation can be chosen
+        hipLaunchKernelGGL(k_ga_need, dim3((unsigned)((s->total_inst + 255) / 256)), dim3(256), 0, st, s->d,
+                           (int)s->total_inst);
+        HIP_OK(hipGetLastError());
         for (int p = 0; p < s->nprob; ++p) {
             const ProbDesc &d = s->hdesc[p];
             const int r = mlp_pool_logits(s->probs[p], s->mlp, s->d.pool_bits + d.pool_word0, d.g.npools,
-                                          d.g.capacity, s->mlp_cnt, s->mlp_feat, s->mlp_logits + d.pool_bit0, st);
+                                          d.g.capacity, s->mlp_cnt, s->mlp_feat, s->mlp_logits + d.pool_bit0, st,
+                                          s->d.need + d.pool_cell0);
             if (r != DABS_OK) return r;
         }
+    }
     hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
                        (int)s->total_inst);
     HIP_OK(hipGetLastError());
@@ -832,7 +869,7 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
         for (int p = 0; p < s->nprob && status == DABS_OK; ++p) {
             const ProbDesc &d = s->hdesc[p];
             status = mlp_pool_logits(s->probs[p], s->mlp, s->d.pool_bits + d.pool_word0, d.g.npools, d.g.capacity,
-                                     s->mlp_cnt, s->mlp_feat, s->mlp_logits + d.pool_bit0, st);
+                                     s->mlp_cnt, s->mlp_feat, s->mlp_logits + d.pool_bit0, st, nullptr);
         }
     if (status == DABS_OK) {
         hipLaunchKernelGGL(k_ga_target, dim3((unsigned)((s->total_inst + 3) / 4)), dim3(256), 0, st, s->d,
@@ -912,7 +949,9 @@ int dabs_batched_set_mlp(dabs_batched *s, const dabs_mlp *m) {
         }
         if (hipMalloc(&s->mlp_cnt, sizeof(int) * cnt) != hipSuccess ||
             hipMalloc(&s->mlp_feat, sizeof(short) * feat) != hipSuccess ||
-            hipMalloc(&s->mlp_logits, sizeof(float) * bits) != hipSuccess)
+            hipMalloc(&s->mlp_logits, sizeof(float) * bits) != hipSuccess ||
+            hipMalloc(&s->d.need, sizeof(int32_t) * s->pool_cells) != hipSuccess ||
+            hipMemset(s->d.need, 0, sizeof(int32_t) * s->pool_cells) != hipSuccess)
             return dabs_fail(DABS_E_NOMEM, "learned-proposal scratch allocation failed");
     }
     s->mlp = m;

@@ -105,6 +105,7 @@ struct BatchDev {
     int32_t *algo, *op;
     int32_t *inst_prob;            // global instance -> problem
     const float *pool_logits;      // nullable: learned logits of every pooled bit
+    int32_t *need;                 // with pool_logits: per pool cell, read by a learned operation this round
     unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round, [3] round cancelled
     uint64_t *record;              // per problem: best pooled vector of the run (kept across restarts)
     const int *cancel;             // nullable: device view of the caller's pinned cancel flag
@@ -150,9 +151,11 @@ int max_n(int wtype);
 
 namespace dabs {
 // Features and (with a network) logits of every entry of P pools of capacity
-// m (dabs_mlp.hip); cnt [P][n] int and feat [P m n][8] bfloat16 are scratch.
+// m (dabs_mlp.hip); cnt [P][n] int and feat [P m n][8] bfloat16 are scratch;
+// need (nullable, [P m]): only the flagged entries' features are computed
+// (and their flags cleared); the logits of the others are left meaningless.
 int mlp_pool_logits(const dabs_problem *p, const dabs_mlp *net, const uint64_t *pool_bits, int P, int m, int *cnt,
-                    short *feat, float *logits, hipStream_t st);
+                    short *feat, float *logits, hipStream_t st, int *need);
 }  // namespace dabs
 
 // Thread-local error text (dabs_capi.hip).

@@ -343,14 +343,24 @@ __global__ void k_pool_counts(const uint64_t *__restrict__ bits, int P, int m, i
 
 // Features of every pooled vector (one workgroup per entry (q, r)).  The
 // local field h_k = W_kk + 2 sum_{j != k} W_kj x_j is accumulated in LDS over
-// the set bits j of the entry (the packed W has a zero diagonal).
+// the set bits j of the entry (the packed W has a zero diagonal).  need
+// (nullable): only the entries flagged there are computed (the parents that
+// this round's learned operations read), and their flags are cleared.
 template <typename WT>
 __global__ __launch_bounds__(256) void k_features(const WT *__restrict__ W, const int *__restrict__ diag,
                                                   const int64_t *__restrict__ rowabs, int64_t ld, int n, int nw,
                                                   int64_t bound, const uint64_t *__restrict__ bits, int m,
-                                                  const int *__restrict__ cnt, short *__restrict__ feat) {
+                                                  const int *__restrict__ cnt, short *__restrict__ feat,
+                                                  int *__restrict__ need) {
     __shared__ int h[4096];
+    __shared__ int wanted;
     const int cell = blockIdx.x, q = cell / m, r = cell % m;
+    if (need) {
+        if (threadIdx.x == 0) wanted = need[cell];
+        __syncthreads();
+        if (!wanted) return;              // the whole workgroup leaves together
+        if (threadIdx.x == 0) need[cell] = 0;
+    }
     const uint64_t *x = bits + (int64_t)cell * nw;
     const uint64_t *best = bits + (int64_t)q * m * nw;
     for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] = diag[k];
@@ -438,7 +448,7 @@ struct dabs_mlp {
 namespace dabs {
 
 int mlp_pool_logits(const dabs_problem *p, const dabs_mlp *net, const uint64_t *pool_bits, int P, int m,
-                    int *cnt, short *feat, float *logits, hipStream_t st) {
+                    int *cnt, short *feat, float *logits, hipStream_t st, int *need) {
     const int n = p->n, nw = (n + 63) / 64;
     const int64_t pn = (int64_t)P * n;
     hipLaunchKernelGGL(k_pool_counts, dim3((unsigned)((pn + 255) / 256)), dim3(256), 0, st, pool_bits, P, m, n, nw,
@@ -446,10 +456,10 @@ int mlp_pool_logits(const dabs_problem *p, const dabs_mlp *net, const uint64_t *
     HIP_OK(hipGetLastError());
     if (p->wtype == DABS_W_I16)
         hipLaunchKernelGGL(k_features<int16_t>, dim3(P * m), dim3(256), 0, st, (const int16_t *)p->W, p->diag,
-                           p->rowabs, p->ld, n, nw, p->bound, pool_bits, m, cnt, feat);
+                           p->rowabs, p->ld, n, nw, p->bound, pool_bits, m, cnt, feat, need);
     else
         hipLaunchKernelGGL(k_features<int32_t>, dim3(P * m), dim3(256), 0, st, (const int32_t *)p->W, p->diag,
-                           p->rowabs, p->ld, n, nw, p->bound, pool_bits, m, cnt, feat);
+                           p->rowabs, p->ld, n, nw, p->bound, pool_bits, m, cnt, feat, need);
     HIP_OK(hipGetLastError());
     if (net && logits) {
         const int64_t N = (int64_t)P * m * n, tiles = (N + 15) / 16;
@@ -513,7 +523,7 @@ int dabs_mlp_pool_features(const dabs_problem *p, const uint64_t *pool_bits_dev,
     int *cnt = nullptr;
     HIP_OK(hipMalloc((void **)&cnt, sizeof(int) * (size_t)npools * p->n));
     int r = mlp_pool_logits(p, nullptr, pool_bits_dev, npools, capacity, cnt, (short *)feat_dev, nullptr,
-                            (hipStream_t)stream);
+                            (hipStream_t)stream, nullptr);
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && r == DABS_OK)
         r = dabs_fail(DABS_E_HIP, "feature kernels failed");
     (void)hipFree(cnt);
@@ -574,7 +584,7 @@ int dabs_mlp_pool_features_noalloc(const dabs_problem *p, const uint64_t *pool_b
     // every count is written by k_pool_counts before k_features reads it, so
     // nothing has to be cleared between calls
     return mlp_pool_logits(p, nullptr, pool_bits_dev, npools, capacity, cnt, (short *)feat_dev, nullptr,
-                           (hipStream_t)stream);
+                           (hipStream_t)stream, nullptr);
 }
 
 int dabs_mlp_labels(const dabs_problem *p, const uint64_t *bits_dev, int64_t count, const uint64_t *ref_dev,
