@@ -177,41 +177,15 @@ def _first_hits(solver_run, progress, rounds_cap, nprob, dev):
     return [float(v) / 1e8 if v >= 0 else None for v in h], r
 
 
-def learned_vs_plain(dev, n=2000, instances=256, npools=4, capacity=50, ref_rounds=100, cap=300,
-                     collect_rounds=500, seeds=(1, 2, 3, 4, 5), epochs=2, lr=2e-3):
-    """Time to target of the plain DABS loop and of the loop with the learned
-    operations on a K2000-like max-cut (complete graph, n = 2000, +-1 weights,
-    seed 0), after training the network on 10^5 pool solutions of a plain run
-    on another graph of the family (seed 1).  Target: the best energy of a
-    plain reference run with another seed after ref_rounds rounds."""
+def _mlp_roofline(dabs, net, feats, labels, dev):
+    """Matrix-core roofline of the network kernels over a training set:
+    algorithmic 2 (8*64 + 64*64 + 64) = 9344 FLOP per sample forward, three
+    times that for forward + backward (the gradient kernel recomputes the
+    forward pass), against the dense bf16 peak."""
     import torch
-    import paper_2207_03069_amd as dabs
-    from paper_2207_03069_amd import train
-
-    def problem(seed):
-        W, _, _ = inputs.maxcut_instance(n, 1.0, seed=seed)
-        return dabs.dabs_problem_create(torch.from_numpy(W).to(dev))
-    T, Bn = round(S_FACTOR * n), n                      # s = 0.1, b = 1
-
-    def params(seed, ops=tuple(range(8))):
-        return dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=seed, capacity=capacity, npools=npools, ops=ops)
-    t0 = time.perf_counter()
-    ptr = problem(1)
-    feats, labels, _ = train.collect(ptr, params(101), instances=instances, rounds=collect_rounds, every=1,
-                                     symmetric=True)          # max-cut: E(x) = E(not x)
-    torch.cuda.synchronize()
-    t_collect = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    net, hist = train.fit(feats, labels, epochs=epochs, batch=1 << 16, lr=lr, seed=0)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t1
     nsamp = int(feats.shape[0])
-    # matrix-core roofline of the network kernels over the whole training set:
-    # algorithmic 2 (8*64 + 64*64 + 64) = 9344 FLOP per sample forward, three
-    # times that for forward + backward (the gradient kernel recomputes the
-    # forward pass)
     logits = torch.empty(nsamp, dtype=torch.float32, device=dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     dabs.dabs_mlp_forward(net, nsamp, feats, logits)               # warm
     ev[0].record()
     dabs.dabs_mlp_forward(net, nsamp, feats, logits)
@@ -221,50 +195,94 @@ def learned_vs_plain(dev, n=2000, instances=256, npools=4, capacity=50, ref_roun
     torch.cuda.synchronize()
     ms_f, ms_g = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     fl_f, fl_g = 9344.0 * nsamp, 3 * 9344.0 * nsamp
-    mlp_roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": 2500.0, "samples": nsamp,
-                "forward": {"ms": ms_f, "achieved": fl_f / ms_f / 1e9, "frac": fl_f / ms_f / 1e9 / 2500.0},
-                "gradient": {"ms": ms_g, "achieved": fl_g / ms_g / 1e9, "frac": fl_g / ms_g / 1e9 / 2500.0}}
-    del feats, labels, ptr, logits
-    prob = problem(0)
-    ref = dabs.dabs_solver_create(prob, params(999), instances)
-    dabs.dabs_solver_autotune(ref)
-    dabs.dabs_solver_run(ref, ref_rounds)
-    prog = torch.zeros(2, dtype=torch.int64, device=dev)
-    dabs.dabs_solver_progress(ref, prog)
-    torch.cuda.synchronize()
-    target = int(prog[1].item())
-    del ref
-    tgt = torch.tensor([target], dtype=torch.int64, device=dev)
-    res = {}
-    for name, ops in (("plain", tuple(range(8))), ("learned", tuple(range(10)))):
-        hits, rounds = [], []
-        for seed in seeds:
-            s = dabs.dabs_solver_create(prob, params(seed, ops), instances)
-            if name == "learned":
-                dabs.dabs_solver_set_mlp(s, net)
-            dabs.dabs_solver_autotune(s)
-            calls = [0]
+    return {"bound": "mfma", "unit": "TFLOP/s", "peak": 2500.0, "samples": nsamp,
+            "forward": {"ms": ms_f, "achieved": fl_f / ms_f / 1e9, "frac": fl_f / ms_f / 1e9 / 2500.0},
+            "gradient": {"ms": ms_g, "achieved": fl_g / ms_g / 1e9, "frac": fl_g / ms_g / 1e9 / 2500.0}}
 
-            def run_one(s=s):
-                # the first call arms the target and starts the device clock
-                dabs.dabs_solver_run(s, 1, tgt if calls[0] == 0 else None)
-                calls[0] += 1
-            h, r = _first_hits(run_one, lambda o, s=s: dabs.dabs_solver_progress(s, o), cap, 1, dev)
-            hits.append(h[0])
-            rounds.append(r if h[0] is not None else None)
-            del s
-        ok = [x for x in hits if x is not None]
-        res[name] = {"seconds_per_seed": hits, "rounds_per_seed": rounds,
-                     "median_s": float(np.median([x if x is not None else np.inf for x in hits])),
-                     "reached": len(ok), "runs": len(hits)}
-    return {"problem": "K2000-like max-cut: complete graph n=%d, +-1 weights, seed 0; %d instances, %d pools x %d, "
-                       "s=0.1 b=1" % (n, instances, npools, capacity),
-            "target_e": target, "target_from": "plain run, seed 999, %d rounds" % ref_rounds, "round_cap": cap,
-            "training": {"problem": "same family, seed 1", "pool_solutions": nsamp // n, "samples": nsamp,
-                         "labels": "bit differs from the nearer of the run's best vector and its complement",
-                         "epochs": len(hist), "loss_per_epoch": hist, "collect_s": t_collect, "train_s": t_train},
-            "mlp_roofline": mlp_roof,
-            "plain": res["plain"], "learned": res["learned"]}
+
+def learned_vs_plain(dev, instances=256, npools=4, capacity=50, ref_rounds=500, cap=500, seeds=range(10),
+                     epochs=2, lr=2e-3):
+    """Time to target of the plain DABS loop and of the loop with the learned
+    operations (all ten operations under the adaptive choice of Section
+    IV-A), on the two families of the learned-proposal workload: a dense
+    n = 2048 int16 QUBO with weights uniform in [-1000, 1000], and the
+    800-node max-cut family G(800, 0.06) with +-1 weights.  Per family: the
+    network is trained (on the GPU, by the library's kernels) on 10^5 pool
+    solutions of a plain run on another member of the family (seed 1); the
+    target is the best energy of a plain reference run with another seed
+    after ref_rounds rounds on the evaluation member (seed 0); each mode runs
+    seeds 0..9 until its first E(BEST) <= target (device clock) or `cap`
+    rounds.  256 instances, 4 pools x 50, s = 0.1, b = 1."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    from paper_2207_03069_amd import train
+    families = {
+        "dense n=2048 int16 U[-1000,1000]": (lambda seed: inputs.dense_qubo(2048, -1000, 1000, seed), False),
+        "max-cut G(800,0.06) +-1": (lambda seed: inputs.maxcut_instance(800, 0.06, seed=seed)[0], True),
+    }
+    out = {}
+    for fname, (make, symmetric) in families.items():
+        def problem(seed):
+            return dabs.dabs_problem_create(torch.from_numpy(make(seed)).to(dev))
+        n = make(0).shape[0]
+        T, Bn = round(S_FACTOR * n), n
+
+        def params(seed, ops=tuple(range(8))):
+            return dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=seed, capacity=capacity, npools=npools, ops=ops)
+        t0 = time.perf_counter()
+        ptr = problem(1)
+        rounds = (100000 + npools * capacity - 1) // (npools * capacity)
+        feats, labels, _ = train.collect(ptr, params(101), instances=instances, rounds=rounds, every=1,
+                                         symmetric=symmetric)
+        torch.cuda.synchronize()
+        t_collect = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        net, hist = train.fit(feats, labels, epochs=epochs, batch=1 << 16, lr=lr, seed=0)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        roof = _mlp_roofline(dabs, net, feats, labels, dev)
+        nsamp = int(feats.shape[0])
+        del feats, labels, ptr
+        prob = problem(0)
+        ref = dabs.dabs_solver_create(prob, params(999), instances)
+        dabs.dabs_solver_autotune(ref)
+        dabs.dabs_solver_run(ref, ref_rounds)
+        prog = torch.zeros(2, dtype=torch.int64, device=dev)
+        dabs.dabs_solver_progress(ref, prog)
+        torch.cuda.synchronize()
+        target = int(prog[1].item())
+        del ref
+        tgt = torch.tensor([target], dtype=torch.int64, device=dev)
+        res = {}
+        for mode, ops in (("plain", tuple(range(8))), ("learned", tuple(range(10)))):
+            per = []
+            for seed in seeds:
+                s = dabs.dabs_solver_create(prob, params(seed, ops), instances)
+                if mode == "learned":
+                    dabs.dabs_solver_set_mlp(s, net)
+                calls = [0]
+
+                def run_one(s=s, calls=calls):
+                    # the first call arms the target and starts the device clock
+                    dabs.dabs_solver_run(s, 1, tgt if calls[0] == 0 else None)
+                    calls[0] += 1
+                h, r = _first_hits(run_one, lambda o, s=s: dabs.dabs_solver_progress(s, o), cap, 1, dev)
+                per.append({"seed": int(seed), "seconds": h[0], "rounds": r if h[0] is not None else None})
+                del s
+            ok = [x["seconds"] for x in per if x["seconds"] is not None]
+            res[mode] = {"success": len(ok), "runs": len(per),
+                         "median_s": float(np.median([x["seconds"] if x["seconds"] is not None else np.inf
+                                                      for x in per])),
+                         "median_rounds": float(np.median([x["rounds"] if x["rounds"] is not None else np.inf
+                                                           for x in per])),
+                         "per_seed": per}
+        out[fname] = {"target_e": target, "target_from": "plain run, seed 999, %d rounds" % ref_rounds,
+                      "round_cap": cap, "instances": instances, "pools": [npools, capacity],
+                      "training": {"problem": "same family, seed 1", "pool_solutions": nsamp // n, "samples": nsamp,
+                                   "epochs": len(hist), "loss_per_epoch": hist, "collect_s": t_collect,
+                                   "train_s": t_train},
+                      "mlp_roofline": roof, "plain": res["plain"], "learned": res["learned"]}
+    return out
 
 
 def tsp_quality(dev, rounds=8, ncity=32):
@@ -392,6 +410,118 @@ def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
                            note="problems run one after another; all reached after the sum of their times")}
 
 
+def _timed_rounds(dabs, s, rounds, dev):
+    """Runs `rounds` rounds of a solver created with DABS_SOLVER_TIME_WALK;
+    returns (wall s, flips, batch-search kernel ms, launches)."""
+    import torch
+    tot = torch.zeros(1, dtype=torch.int64, device=dev)
+    dabs.dabs_solver_timing(s, reset=True)
+    dabs.dabs_solver_state(s, total_flips=tot)
+    torch.cuda.synchronize()
+    f0 = int(tot.item())
+    t0 = time.perf_counter()
+    dabs.dabs_solver_run(s, rounds)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    walk_ms, launches, _ = dabs.dabs_solver_timing(s, reset=True)
+    dabs.dabs_solver_state(s, total_flips=tot)
+    torch.cuda.synchronize()
+    return wall, int(tot.item()) - f0, walk_ms, launches
+
+
+def sparse_workloads(dev, lds_peak):
+    """The sparse search kernel (deltas in LDS, a flip touching only the
+    nonzeros of its row) on the sparse families of Section VI: a G22-like
+    max-cut graph (n = 2000, p = 0.01, +-1 weights: ~20 nonzeros per row) and
+    a resolution-1 Ising model on an annealer-shaped graph (5,627 nodes,
+    40,279 edges, degree <= 15; Section II-C).  2048 instances, 8 pools x 100,
+    s = 0.1, b = 1, 4 timed rounds after 1 warm-up round.  Algorithmic bytes
+    per flip: 4 per nonzero of the flipped row (its W words); the rules'
+    comparison pass over the n deltas reads 4n bytes of LDS per flip (Steps
+    1-2), reported against the measured LDS peak."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    out = {}
+    cases = []
+    W, _, _ = inputs.maxcut_instance(2000, 0.01, seed=0, dtype=np.int32)
+    rp, col, val = inputs.csr_from_dense(W)
+    cases.append(("G22-like max-cut n=2000 p=0.01 +-1",
+                  lambda: dabs.dabs_problem_create_csr(torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev),
+                                                       torch.from_numpy(val).to(dev), 2000), 2000,
+                  (len(col) - 2000) / 2000.0))
+    n, m = 5627, 40279
+    edges = inputs.sparse_graph(n, m, 15, 0)
+    J, h = inputs.ising_instance(n, edges, 1, 1)
+
+    def ising():
+        p, _ = dabs.dabs_problem_create_ising(n, torch.from_numpy(edges.astype(np.int32)).to(dev),
+                                              torch.from_numpy(J.astype(np.int32)).to(dev),
+                                              torch.from_numpy(h.astype(np.int32)).to(dev))
+        return p
+    cases.append(("annealer-shaped Ising r=1 n=5627 m=40279", ising, n, 2.0 * m / n))
+    for name, make, nn, deg in cases:
+        p = make()
+        g = dabs.ga_params(T=round(0.1 * nn), Bn=nn, tau=TAU, seed=0, capacity=CAPACITY, npools=NPOOLS,
+                           flags=dabs.DABS_SOLVER_TIME_WALK)
+        s = dabs.dabs_solver_create(p, g, 2048)
+        dabs.dabs_solver_run(s, 1)
+        wall, flips, walk_ms, launches = _timed_rounds(dabs, s, 4, dev)
+        wb = flips * 4.0 * deg / (walk_ms / 1e3) / 1e9
+        lb = flips * 4.0 * nn / (walk_ms / 1e3) / 1e9
+        out[name] = {"flips_per_s": flips / wall, "flips": flips, "wall_s": wall,
+                     "kernel_ms_per_launch": walk_ms / max(launches, 1),
+                     "nonzeros_per_row": deg, "w_bytes_per_flip": 4.0 * deg, "w_GB_per_s": wb,
+                     "delta_scan_lds_bytes_per_flip": 4 * nn, "delta_scan_lds_GB_per_s": lb,
+                     "lds_peak_GB_per_s": lds_peak, "lds_frac": lb / lds_peak,
+                     "dense_row_bytes_would_be": 2 * nn}
+        del s, p
+    return out
+
+
+def small_n(dev, lds_peak):
+    """W rows from LDS.  (1) The 24-bit correctness workload: n = 24, int16
+    W uniform in [-128, 127] (seed 0), 64 tabu-greedy instances (tau = 4) x
+    2000 flips through dabs_search (the rows come from the workgroup's LDS
+    copy of W).  (2) 4096 instances of the generational loop on a dense
+    n = 128 int16 problem: the autotuner's times of the L2-row variants and
+    of the LDS-row variant on the same items."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    W = inputs.dense_qubo(24, -128, 127, 0)
+    p = dabs.dabs_problem_create(torch.from_numpy(W).to(dev))
+    X = torch.from_numpy(inputs.pack_bits(inputs.random_bits(64, 24, 0)).view(np.int64)).to(dev)
+    best = torch.zeros_like(X)
+    be = torch.zeros(64, dtype=torch.int64, device=dev)
+    e = torch.zeros(64, dtype=torch.int64, device=dev)
+    sp = dabs.dabs_search_params(rule=dabs.DABS_TABU_GREEDY, T=2000, tau=4, greedy_cap=0, seed=0, phase=0, inst0=0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    x = X.clone()
+    dabs.dabs_search(p, sp, x, None, best, be, e)                      # warm
+    x = X.clone()
+    torch.cuda.synchronize()
+    ev[0].record()
+    dabs.dabs_search(p, sp, x, None, best, be, e)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    c1 = {"workload": "n=24 int16 U[-128,127] seed 0, 64 tabu-greedy instances (tau 4) x 2000 flips",
+          "ms": ms, "flips_per_s": 64 * 2000 / (ms / 1e3), "best_energy": int(be.min().item()),
+          "lds_row_bytes_per_flip": 48, "lds_GB_per_s": 64 * 2000 * 48 / (ms / 1e3) / 1e9,
+          "note": "one launch of 16 workgroups: latency of the 2000-flip chain, not bandwidth"}
+    W = inputs.dense_qubo(128, -1000, 1000, 1)
+    p2 = dabs.dabs_problem_create(torch.from_numpy(W).to(dev))
+    g = dabs.ga_params(T=13, Bn=10 * 128, tau=TAU, seed=0, capacity=CAPACITY, npools=NPOOLS)
+    s = dabs.dabs_solver_create(p2, g, 4096)
+    dabs.dabs_solver_run(s, 2)
+    tune_ms, choice = dabs.dabs_solver_autotune(s)
+    row = tune_ms[0]
+    return {"c1": c1,
+            "n128_4096_instances": {"variant_ms": {"l2_rows_capped": row[0], "l2_rows_uncapped": row[1],
+                                                   "lds_rows": row[2]},
+                                    "chosen": ["l2_rows_capped", "l2_rows_uncapped", "lds_rows"][choice[0]],
+                                    "lds_peak_GB_per_s": lds_peak}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +532,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tsp", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 256 MiB device copy")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -510,6 +642,14 @@ def main():
                                             for x in per_seed])),
                "per_seed": per_seed,
                "note": "device clock (100 MHz) from the arming call to the first E(BEST) <= target"}
+    sparse = None
+    if not args.no_sparse:
+        print("bench: sparse workloads ...", file=sys.stderr, flush=True)
+        sparse = sparse_workloads(dev, peaks["lds"]["GB/s"])
+    small = None
+    if not args.no_small:
+        print("bench: small n (W in LDS) ...", file=sys.stderr, flush=True)
+        small = small_n(dev, peaks["lds"]["GB/s"])
     learned = None
     if not args.no_learned:
         print("bench: learned vs plain ...", file=sys.stderr, flush=True)
@@ -542,6 +682,8 @@ def main():
         "time_to_target_learned_vs_plain": learned,
         "time_to_target_batched_vs_single": batched,
         "tsp": tsp,
+        "sparse": sparse,
+        "small_n_lds_rows": small,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
