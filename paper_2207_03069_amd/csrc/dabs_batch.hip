@@ -266,10 +266,16 @@ __global__ __launch_bounds__(256) void k_sort_items(BatchDev b, int2 *items, con
 // pool's instances in increasing order; insert only when strictly better
 // than the worst entry and no identical vector is pooled; ascending energies,
 // a newcomer after equal energies.  The energy / algorithm / operation
-// columns are worked on in LDS; each lane moves only its own words.
-__global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pools) {
+// columns are worked on in LDS; the position search and the moves of the
+// rows and columns below the insertion point are spread over the lanes.
+// bits_lds: with a nonzero size of dynamic LDS (at least capacity x nwords
+// words for every pool of the batch), the pool's bits are worked on in LDS
+// as well and written back at the end.
+__global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pools, int bits_lds) {
     __shared__ long long se[POOL_MAX];
     __shared__ int sal[POOL_MAX], sop[POOL_MAX];
+    __shared__ uint64_t pk[WAVE];
+    extern __shared__ uint64_t sbits[];
     if (b.ctr[3]) return;                 // cancelled round: no packets
     const int2 pq = pools[blockIdx.x];
     const ProbDesc &d = b.desc[pq.x];
@@ -278,55 +284,114 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     const int64_t cell = d.pool_cell0 + (int64_t)q * m;
     int64_t *pe = b.pool_e + cell;
     int32_t *pal = b.pool_algo + cell, *pop = b.pool_op + cell;
-    uint64_t *pbits = b.pool_bits + d.pool_word0 + (int64_t)q * m * nw;
+    uint64_t *gbits = b.pool_bits + d.pool_word0 + (int64_t)q * m * nw;
+    uint64_t *pbits = bits_lds ? sbits : gbits;
     for (int r = lane; r < m; r += WAVE) {
         se[r] = pe[r];
         sal[r] = pal[r];
         sop[r] = pop[r];
     }
+    if (bits_lds)
+        for (int w = lane; w < m * nw; w += WAVE) sbits[w] = gbits[w];
     __syncthreads();
-    for (int i = q; i < d.instances; i += P) {
-        const int64_t gi = d.inst0 + i;
-        const int64_t e = b.best_e[gi];
-        if (!(e < se[m - 1])) continue;
-        const uint64_t *bits = b.best + d.inst_word0 + (int64_t)i * nw;
-        // an identical vector has the same energy, unless the entry is one of
-        // the initial random vectors (energy +inf, never evaluated): only
-        // those entries are compared bit for bit, one entry per lane
-        bool dup = false;
-        for (int r0 = 0; r0 < m && !dup; r0 += WAVE) {
-            const int r = r0 + lane;
-            bool same = false;
-            if (r < m && (se[r] == e || se[r] == E_INF)) {
-                same = true;
-                for (int w = 0; w < nw; ++w) same = same && pbits[(int64_t)r * nw + w] == bits[w];
+    // the pool's packets in instance order, 64 at a time: the lanes load 64
+    // energies at once and only those below the current worst entry are
+    // visited (the worst entry never rises, so the others stay rejected)
+    for (int i0 = q; i0 < d.instances; i0 += P * WAVE) {
+        const int il = i0 + lane * P;
+        const int64_t el = il < d.instances ? b.best_e[d.inst0 + il] : E_INF;
+        uint64_t cand = __builtin_amdgcn_ballot_w64(el < se[m - 1]);
+        // the packet's words, one per lane (nw <= 64); the next candidate's
+        // are loaded while the current one is processed
+        auto words_of = [&](uint64_t c) {
+            const int64_t iw = d.inst_word0 + (int64_t)(i0 + (int)__builtin_ctzll(c) * P) * nw;
+            return lane < nw ? b.best[iw + lane] : 0ull;
+        };
+        uint64_t nextw = cand ? words_of(cand) : 0ull;
+        while (cand) {
+            const int t = (int)__builtin_ctzll(cand);
+            cand &= cand - 1;
+            const uint64_t curw = nextw;
+            if (cand) nextw = words_of(cand);
+            const int i = i0 + t * P;
+            const int64_t gi = d.inst0 + i;
+            const int64_t e = (int64_t)readlane64((uint64_t)el, t);
+            if (!(e < se[m - 1])) continue;
+            if (lane < nw) pk[lane] = curw;
+            __syncthreads();
+            const uint64_t *bits = pk;
+            // an identical vector has the same energy, unless the entry is one of
+            // the initial random vectors (energy +inf, never evaluated): only
+            // those entries are compared bit for bit, one entry per lane
+            bool dup = false;
+            for (int r0 = 0; r0 < m && !dup; r0 += WAVE) {
+                const int r = r0 + lane;
+                bool same = false;
+                if (r < m && (se[r] == e || se[r] == E_INF)) {
+                    uint64_t diff = 0;           // every word read (independent loads), no early exit
+                    for (int w = 0; w < nw; ++w) diff |= pbits[(int64_t)r * nw + w] ^ bits[w];
+                    same = diff == 0;
+                }
+                dup = __builtin_amdgcn_ballot_w64(same) != 0;
             }
-            dup = __builtin_amdgcn_ballot_w64(same) != 0;
-        }
-        if (dup) continue;
-        int pos = 0;
-        while (pos < m && se[pos] <= e) ++pos;
-        for (int r = m - 1; r > pos; --r)
-            for (int w = lane; w < nw; w += WAVE) pbits[(int64_t)r * nw + w] = pbits[(int64_t)(r - 1) * nw + w];
-        for (int w = lane; w < nw; w += WAVE) pbits[(int64_t)pos * nw + w] = bits[w];
-        __syncthreads();
-        if (lane == 0) {
-            for (int r = m - 1; r > pos; --r) {
-                se[r] = se[r - 1];
-                sal[r] = sal[r - 1];
-                sop[r] = sop[r - 1];
+            if (dup) continue;
+            // position: the number of entries with energy <= e (they are sorted)
+            int cnt = 0;
+            for (int r = lane; r < m; r += WAVE) cnt += se[r] <= e ? 1 : 0;
+            const int pos = (int)wave_sum64(cnt);
+            // rows pos .. m-2 move down one row: the words [pos nw, (m-1) nw) go
+            // nw words up, in blocks of 4 x 64 words taken from the top, every
+            // block loaded before it is stored
+            const int64_t lo = (int64_t)pos * nw;
+            for (int64_t top = (int64_t)(m - 1) * nw; top > lo; top -= 4 * WAVE) {
+                uint64_t v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t idx = top - 1 - (k * WAVE + lane);
+                    v[k] = idx >= lo ? pbits[idx] : 0ull;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t idx = top - 1 - (k * WAVE + lane);
+                    if (idx >= lo) pbits[idx + nw] = v[k];
+                }
+                __syncthreads();
             }
-            se[pos] = e;
-            sal[pos] = b.algo[gi];
-            sop[pos] = b.op[gi];
+            for (int w = lane; w < nw; w += WAVE) pbits[(int64_t)pos * nw + w] = bits[w];
+            // the columns likewise, 64 entries at a time from the top
+            for (int top = m - 1; top > pos; top -= WAVE) {
+                const int r = top - lane;
+                long long ve = 0;
+                int va = 0, vo = 0;
+                if (r > pos) {
+                    ve = se[r - 1];
+                    va = sal[r - 1];
+                    vo = sop[r - 1];
+                }
+                __syncthreads();
+                if (r > pos) {
+                    se[r] = ve;
+                    sal[r] = va;
+                    sop[r] = vo;
+                }
+                __syncthreads();
+            }
+            if (lane == 0) {
+                se[pos] = e;
+                sal[pos] = b.algo[gi];
+                sop[pos] = b.op[gi];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     for (int r = lane; r < m; r += WAVE) {
         pe[r] = se[r];
         pal[r] = sal[r];
         pop[r] = sop[r];
     }
+    if (bits_lds)
+        for (int w = lane; w < m * nw; w += WAVE) gbits[w] = sbits[w];
 }
 
 // After the packets of a round (one workgroup per problem): the record (the
@@ -434,6 +499,7 @@ struct dabs_batched {
     int *item0;                        // device, first item of each problem
     int2 *pool_list;                   // device, (problem, pool)
     int npool_list;
+    int insert_lds;                    // dynamic LDS of the pool insertion (0: pool bits in global memory)
     struct Cls { int wtype, slots, begin, count, variant, lds_bytes; };
     std::vector<Cls> classes;
     hipStream_t side[MAX_CLASSES];
@@ -569,8 +635,14 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         s->classes.push_back(c);
     }
     std::vector<int2> pl;
-    for (int p = 0; p < nprob; ++p)
+    int64_t pool_words_max = 0;
+    for (int p = 0; p < nprob; ++p) {
         for (int q = 0; q < s->hdesc[p].g.npools; ++q) pl.push_back(make_int2(p, q));
+        pool_words_max = std::max<int64_t>(pool_words_max, (int64_t)s->hdesc[p].g.capacity * s->hdesc[p].nw);
+    }
+    // the pool bits go to LDS when every pool's fit in 40 KB (beside the
+    // 16 KB of energy / algorithm / operation columns)
+    s->insert_lds = pool_words_max * 8 <= 40960 ? (int)(pool_words_max * 8) : 0;
     s->npool_list = (int)pl.size();
     std::vector<int32_t> ip(inst);
     for (int p = 0; p < nprob; ++p)
@@ -677,7 +749,8 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
         HIP_OK(hipEventRecord(s->ev[2 * s->nev + 1], st));
         s->nev++;
     }
-    hipLaunchKernelGGL(k_pool_insert, dim3(s->npool_list), dim3(64), 0, st, s->d, s->pool_list);
+    hipLaunchKernelGGL(k_pool_insert, dim3(s->npool_list), dim3(64), s->insert_lds, st, s->d, s->pool_list,
+                       s->insert_lds > 0 ? 1 : 0);
     HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(k_pool_record, dim3(s->nprob), dim3(256), 0, st, s->d);
     HIP_OK(hipGetLastError());
