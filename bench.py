@@ -339,13 +339,18 @@ def tsp_quality(dev, rounds=8, ncity=32):
             "nearest_neighbour_length": nn}
 
 
-def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
+TARGETS_FILE = os.path.join(ROOT, "tests", "golden", "batched_targets.json")
+
+
+def batched_vs_single(dev, nprob=256, inst=32, cap=10):
     """The many-problem workload: 256 dense int16 QUBOs, n log-uniform in
-    [256, 4096), U[-1000, 1000].  Target of each problem: its best energy after
-    ref_rounds rounds of a reference run with other seeds.  Batched: all
-    problems in one graph-replayed round; single: one solver per problem, run
-    one after another (one launch sequence per problem).  Same seeds, so both
-    follow the same trajectories; the comparison is the time to the targets."""
+    [256, 4096), U[-1000, 1000].  Target of each problem: the best energy of
+    the oracle's loop on it with a fixed prefix budget (instances 0..7, 3
+    rounds, other seeds; written by tests/golden/make_batched_targets.py).
+    Batched: all problems in one graph-replayed round; single: one solver per
+    problem, run one after another (one launch sequence per problem).  Same
+    seeds, so both follow the same trajectories; the comparison is the time
+    to the targets."""
     import torch
     import paper_2207_03069_amd as dabs
     t0 = time.perf_counter()
@@ -358,13 +363,8 @@ def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
     def params(seed0):
         return [dabs.ga_params(T=max(1, round(0.1 * n)), Bn=n, tau=TAU, seed=seed0 + p, capacity=16, npools=2)
                 for p, n in enumerate(sizes)]
-    ref = dabs.dabs_batched_create(probs, params(50000), [inst] * nprob)
-    dabs.dabs_batched_run(ref, ref_rounds, None, use_graph=True)
-    prog = torch.zeros((nprob, 2), dtype=torch.int64, device=dev)
-    dabs.dabs_batched_progress(ref, prog)
-    torch.cuda.synchronize()
-    targets = prog[:, 1].clone()
-    del ref
+    with open(TARGETS_FILE) as fh:
+        targets = torch.tensor(json.load(fh)["targets"][:nprob], dtype=torch.int64, device=dev)
     # batched
     b = dabs.dabs_batched_create(probs, params(1), [inst] * nprob)
     tune_ms, tune_choice = dabs.dabs_batched_autotune(b)
@@ -401,7 +401,8 @@ def batched_vs_single(dev, nprob=256, inst=32, ref_rounds=3, cap=6):
                 "max_s": float(max(ok)) if ok else None, "sum_s": float(sum(ok))}
     sb, ss = summary(hb), summary(hs)
     return {"problems": nprob, "instances_per_problem": inst, "n_min": min(sizes), "n_max": max(sizes),
-            "targets": "best energy per problem after %d rounds of a reference run (other seeds)" % ref_rounds,
+            "targets": "per problem the oracle's best energy with instances 0..7 x 3 rounds (other seeds), "
+                       "tests/golden/batched_targets.json",
             "round_cap": cap, "load_s": t_load,
             "batched": dict(sb, time_all_reached_s=sb["max_s"], wall_s=wall_b, rounds=rb,
                             autotune=[{"wtype": c[0], "slots": c[1], "items": c[2], "variant_ms": m, "chosen": c[3]}

@@ -96,3 +96,18 @@ def test_qap_table3_shape_fits_the_device_bound():
     W = inputs.qap_qubo(F, D, 200000)
     B = oracle.delta_bound(W)
     assert (1 << 23) < B < (1 << 26) - 2
+
+
+def test_batched_targets_file_reproduces():
+    """The stored time-to-target energies of the many-problem workload are
+    what the committed script computes with the oracle (three of the
+    smallest problems recomputed)."""
+    import importlib.util
+    path = os.path.join(GOLD, "make_batched_targets.py")
+    spec = importlib.util.spec_from_file_location("make_batched_targets", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    stored = json.load(open(os.path.join(GOLD, "batched_targets.json")))["targets"]
+    sizes = inputs.batched_sizes(256, seed=0)
+    for p in np.argsort(sizes)[:3]:
+        assert mod.target(int(p)) == stored[int(p)], p
