@@ -334,7 +334,8 @@ def tsp_quality(dev, rounds=8, ncity=32):
     return {"workload": "TSP 32 cities -> one-hot QUBO n=1024, int32 W, A=2*max d=%d; 8192 instances, "
                         "8 pools x 100, two-point crossover, 1%% mutation, s=0.1 b=1" % A,
             "rounds": rounds, "wall_s": wall, "flips": int(tot.item()), "flips_per_s": int(tot.item()) / wall,
-            "best_energy": best_e, "best_is_tour": tour_ok, "tour_length": length,
+            "best_energy": best_e,
+        "adaptive_choice": adaptive, "best_is_tour": tour_ok, "tour_length": length,
             "energy_check": (best_e == 2 * length - 2 * ncity * A) if tour_ok else None,
             "nearest_neighbour_length": nn}
 
@@ -576,6 +577,18 @@ def main():
     torch.cuda.synchronize()
     flips = int(tot.item()) - f0
     best_e = int(prog[1].item())
+    st = torch.zeros(dabs.DABS_STATS, dtype=torch.int64, device=dev)
+    dabs.dabs_solver_stats(solver, st)
+    st = st.cpu().numpy()
+    op_names = ["Random", "Best", "Mutation", "Crossover", "Xrossover", "Zero", "One", "IntervalZero"]
+    algo_names = {2: "MaxMin", 3: "CyclicMin", 4: "RandomMin", 5: "PositiveMin", 6: "TwoNeighbor"}
+    adaptive = {"note": "uses and pool entries over the warm-up and timed rounds (Section IV-A's adaptive choice; "
+                        "the bookkeeping behind Section VI-D's tables)",
+                "operations": {op_names[k]: {"used": int(st[k]), "entered_pool": int(st[24 + k])} for k in range(8)},
+                "algorithms": {v: {"used": int(st[16 + k]), "entered_pool": int(st[40 + k])}
+                               for k, v in algo_names.items()},
+                "record_found_by": {"operation": op_names[st[48]] if 0 <= st[48] < 8 else int(st[48]),
+                                    "algorithm": algo_names.get(int(st[49]), int(st[49]))}}
     del solver
 
     # roofline of the batch-search kernel.  Algorithmic bytes per flip: one

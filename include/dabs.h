@@ -288,6 +288,18 @@ int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream);
 int dabs_solver_record(const dabs_solver *s, uint64_t *bits_dev, int64_t *out_dev, void *stream);
 
 /*
+ * Counters of the adaptive choice (Section IV-A), the bookkeeping behind the
+ * per-operation and per-algorithm tables of Section VI-D.  out_dev int64
+ * [DABS_STATS]: how many times each genetic operation (16 slots, dabs_op)
+ * and each main algorithm (8 slots, dabs_rule) was chosen, how many of their
+ * packets entered a pool (same slots), then the operation and algorithm
+ * columns of the record's entry when the record was last improved (-1 before
+ * the first round).  Cancelled rounds count nothing.
+ */
+#define DABS_STATS 50
+int dabs_solver_stats(const dabs_solver *s, int64_t *out_dev, void *stream);
+
+/*
  * Cancellation (Section III-B: the device repeats batch searches until the
  * host requests termination).  flag_host is a 32-bit word of pinned host
  * memory that the device can read (hipHostMalloc, or a tensor created with
@@ -353,6 +365,8 @@ int dabs_batched_flips(const dabs_batched *b, int64_t *total_flips_dev, void *st
 int dabs_batched_timing(dabs_batched *b, double *out_host, int32_t reset);
 /* As dabs_solver_record for problem `prob` (the round counter is the batch's). */
 int dabs_batched_record(const dabs_batched *b, int32_t prob, uint64_t *bits_dev, int64_t *out_dev, void *stream);
+/* As dabs_solver_stats for problem `prob`. */
+int dabs_batched_stats(const dabs_batched *b, int32_t prob, int64_t *out_dev, void *stream);
 /* As dabs_solver_set_cancel, for every problem of the batch (graph replays
  * included: the flag is read by the device). */
 int dabs_batched_set_cancel(dabs_batched *b, const volatile int32_t *flag_host);

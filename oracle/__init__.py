@@ -104,7 +104,7 @@ def lib():
         L.orc_solve.argtypes = [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, i32]
         L.orc_solve.restype = i64
         L.orc_solve_ex.argtypes = [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, i32,
-                                   SCORE_FN, P, P, P, P, P]
+                                   SCORE_FN, P, P, P, P, P, P]
         L.orc_solve_ex.restype = i64
         L.orc_target_from_pools.argtypes = [i32, P, P, P, P, P, P, u32, u32, P, P, P]
         L.orc_randmin_q.argtypes = [i64, i64, i32]
@@ -284,6 +284,7 @@ def solve(W, g: GAParams, instances: int, rounds: int, verify=False, score=None,
             tick(int(rnd))
         cb = SCORE_FN(_tick)
     rb = np.zeros(max(rounds, 1), dtype=np.int64)
+    st = np.zeros(50, dtype=np.int64)
     pb = np.zeros((P, m, n), dtype=np.uint8)
     pe = np.zeros((P, m), dtype=np.int64)
     pa = np.zeros((P, m), dtype=np.int32)
@@ -299,12 +300,12 @@ def solve(W, g: GAParams, instances: int, rounds: int, verify=False, score=None,
     nr = C.c_int32()
     f = lib().orc_solve_ex(_p(W), n, C.byref(g), instances, rounds, _p(pb), _p(pe), _p(pa), _p(po),
                            _p(x), _p(e), _p(ph), _p(ins), _p(tg), _p(pk), int(verify), cb, None,
-                           _p(bb), C.byref(be), C.byref(nr), _p(rb))
+                           _p(bb), C.byref(be), C.byref(nr), _p(rb), _p(st))
     if f < 0:
         raise RuntimeError("oracle solve failed (%d)" % f)
     return dict(flips=int(f), pool_bits=pb, pool_e=pe, pool_algo=pa, pool_op=po, x=x, e=e, ph=ph,
                 inserts=ins[:rounds], targets=tg, packets=pk, best_bits=bb, best_e=int(be.value),
-                restarts=int(nr.value), round_best=rb[:rounds])
+                restarts=int(nr.value), round_best=rb[:rounds], stats=st)
 
 
 def target_from_pools(g: GAParams, pool_bits, inst, rnd=0, pool_e=None, pool_algo=None, pool_op=None,

@@ -842,15 +842,23 @@ static int pools_merged(const pools_t *p, int32_t h)
  * g->flags the pools restart when merged (R24); best_bits / best_e (nullable)
  * receive the best pooled vector seen over all rounds and epochs and
  * restarts_out the number of restarts; round_best (nullable, [rounds]) the
- * record's energy after each round.  Returns total flips or a negative
+ * record's energy after each round; stats (nullable, [ORC_STATS]) how often
+ * each genetic operation and main algorithm was chosen and how often its
+ * packet entered a pool, and the operation / algorithm columns of the
+ * record's entry when it was last improved (the bookkeeping behind Section
+ * VI-D's tables).  Returns total flips or a negative
  * code. */
 int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t instances,
                      int32_t rounds, uint8_t *pool_bits, int64_t *pool_e, int32_t *pool_algo,
                      int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
                      int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify,
                      orc_score_fn score, void *score_ctx, uint8_t *best_bits, int64_t *best_e,
-                     int32_t *restarts_out, int64_t *round_best)
+                     int32_t *restarts_out, int64_t *round_best, int64_t *stats)
 {
+    if (stats) {
+        memset(stats, 0, sizeof(int64_t) * ORC_STATS);
+        stats[ORC_STAT_REC_OP] = stats[ORC_STAT_REC_ALGO] = -1;
+    }
     if (n < 1 || instances < 1 || g->npools < 1 || g->capacity < 1) return -1;
     if (g->n_algos < 1 || g->n_ops < 1) return -1;
     pools_t p = {n, g->capacity, g->npools, pool_bits, pool_e, pool_algo, pool_op};
@@ -888,6 +896,14 @@ int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_
         for (int32_t i = 0; i < instances; i++) {
             int32_t pos = pool_insert(&p, (int32_t)(i % g->npools), bb + (int64_t)i * n, eb[i], al[i], op[i]);
             if (inserts) inserts[(int64_t)r * instances + i] = pos;
+            if (stats) {
+                stats[ORC_STAT_USE_OP + op[i]]++;
+                stats[ORC_STAT_USE_ALGO + al[i]]++;
+                if (pos >= 0) {
+                    stats[ORC_STAT_INS_OP + op[i]]++;
+                    stats[ORC_STAT_INS_ALGO + al[i]]++;
+                }
+            }
         }
         if (packets_out) memcpy(packets_out, eb, sizeof(int64_t) * (size_t)instances);
         /* the run's best pooled vector so far (kept across restarts) */
@@ -895,6 +911,10 @@ int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_
             if (p.e[(int64_t)q * p.cap] < record_e) {
                 record_e = p.e[(int64_t)q * p.cap];
                 memcpy(record, entry_bits(&p, q, 0), (size_t)n);
+                if (stats) {
+                    stats[ORC_STAT_REC_OP] = p.op[(int64_t)q * p.cap];
+                    stats[ORC_STAT_REC_ALGO] = p.algo[(int64_t)q * p.cap];
+                }
             }
         if (round_best) round_best[r] = record_e;
         if ((g->flags & ORC_GA_RESTART) && pools_merged(&p, g->merge_hamming)) {
@@ -920,7 +940,7 @@ int64_t orc_solve(const int32_t *W, int32_t n, const orc_ga_params *g, int32_t i
 {
     return orc_solve_ex(W, n, g, instances, rounds, pool_bits, pool_e, pool_algo, pool_op, x_out,
                         e_out, ph_out, inserts, targets_out, packets_out, verify, NULL, NULL, NULL,
-                        NULL, NULL, NULL);
+                        NULL, NULL, NULL, NULL);
 }
 
 /* One target drawn by ga_target from pools the caller supplies (bits

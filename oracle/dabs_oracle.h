@@ -80,7 +80,12 @@ int64_t orc_solve_ex(const int32_t *W, int32_t n, const orc_ga_params *g, int32_
                      int32_t *pool_op, uint8_t *x_out, int64_t *e_out, uint32_t *ph_out,
                      int32_t *inserts, uint8_t *targets_out, int64_t *packets_out, int32_t verify,
                      orc_score_fn score, void *score_ctx, uint8_t *best_bits, int64_t *best_e,
-                     int32_t *restarts_out, int64_t *round_best);
+                     int32_t *restarts_out, int64_t *round_best, int64_t *stats);
+
+/* layout of orc_solve_ex's stats: uses of operations 0..15, of algorithms
+ * 0..7, pool entries made by each, then the record's operation and algorithm */
+enum { ORC_STAT_USE_OP = 0, ORC_STAT_USE_ALGO = 16, ORC_STAT_INS_OP = 24, ORC_STAT_INS_ALGO = 40,
+       ORC_STAT_REC_OP = 48, ORC_STAT_REC_ALGO = 49, ORC_STATS = 50 };
 
 void orc_target_from_pools(int32_t n, const orc_ga_params *g, uint8_t *pool_bits, int64_t *pool_e,
                            int32_t *pool_algo, int32_t *pool_op, const float *logits, uint32_t round,

@@ -66,6 +66,8 @@ _SIGS = {
     "dabs_bandwidth_probe": ([C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "dabs_ising_to_qubo": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "dabs_solver_record": ([_P, _P, _P, _P], C.c_int),
+    "dabs_solver_stats": ([_P, _P, _P], C.c_int),
+    "dabs_batched_stats": ([_P, C.c_int32, _P, _P], C.c_int),
     "dabs_solver_set_cancel": ([_P, _P], C.c_int),
     "dabs_batched_record": ([_P, C.c_int32, _P, _P, _P], C.c_int),
     "dabs_batched_set_cancel": ([_P, _P], C.c_int),
@@ -392,6 +394,20 @@ def dabs_batched_flips(b: Batched, out, stream=None):
 def dabs_solver_record(s: Solver, bits=None, out=None, stream=None):
     """bits [nwords] int64, out [3] int64 = (energy, restarts, rounds)."""
     _check(lib().dabs_solver_record(s.handle, _ptr(bits), _ptr(out), _stream(stream)))
+
+
+DABS_STATS = 50
+
+
+def dabs_solver_stats(s: Solver, out, stream=None):
+    """out [50] int64: uses of operations (16) and algorithms (8), their
+    packets that entered a pool (16 + 8), the record's operation and
+    algorithm."""
+    _check(lib().dabs_solver_stats(s.handle, _ptr(out), _stream(stream)))
+
+
+def dabs_batched_stats(b: Batched, prob: int, out, stream=None):
+    _check(lib().dabs_batched_stats(b.handle, prob, _ptr(out), _stream(stream)))
 
 
 def dabs_solver_set_cancel(s: Solver, flag):

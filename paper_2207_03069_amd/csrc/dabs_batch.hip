@@ -275,6 +275,7 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     __shared__ long long se[POOL_MAX];
     __shared__ int sal[POOL_MAX], sop[POOL_MAX];
     __shared__ uint64_t pk[WAVE];
+    __shared__ unsigned int hist[STAT_WORDS];
     extern __shared__ uint64_t sbits[];
     if (b.ctr[3]) return;                 // cancelled round: no packets
     const int2 pq = pools[blockIdx.x];
@@ -293,6 +294,13 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     }
     if (bits_lds)
         for (int w = lane; w < m * nw; w += WAVE) sbits[w] = gbits[w];
+    if (lane < STAT_WORDS) hist[lane] = 0;
+    __syncthreads();
+    // the operations and algorithms the pool's instances used this round
+    for (int i = q + lane * P; i < d.instances; i += P * WAVE) {
+        atomicAdd(&hist[STAT_USE_OP + (b.op[d.inst0 + i] & 15)], 1u);
+        atomicAdd(&hist[STAT_USE_ALGO + (b.algo[d.inst0 + i] & 7)], 1u);
+    }
     __syncthreads();
     // the pool's packets in instance order, 64 at a time: the lanes load 64
     // energies at once and only those below the current worst entry are
@@ -381,6 +389,8 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
                 se[pos] = e;
                 sal[pos] = b.algo[gi];
                 sop[pos] = b.op[gi];
+                hist[STAT_INS_OP + (b.op[gi] & 15)]++;
+                hist[STAT_INS_ALGO + (b.algo[gi] & 7)]++;
             }
             __syncthreads();
         }
@@ -392,6 +402,8 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     }
     if (bits_lds)
         for (int w = lane; w < m * nw; w += WAVE) gbits[w] = sbits[w];
+    if (lane < STAT_WORDS && hist[lane])
+        atomicAdd(&b.stats[(int64_t)pq.x * STAT_WORDS + lane], (unsigned long long)hist[lane]);
 }
 
 // After the packets of a round (one workgroup per problem): the record (the
@@ -420,7 +432,11 @@ __global__ __launch_bounds__(256) void k_pool_record(BatchDev b) {
         for (int w = tid; w < nw; w += blockDim.x) b.record[d.rec_word0 + w] = best[w];
     const uint32_t epoch = (uint32_t)d.epoch;
     __syncthreads();                      // every thread has read record_e and epoch
-    if (better && tid == 0) d.record_e = eb;
+    if (better && tid == 0) {
+        d.record_e = eb;
+        d.record_op = b.pool_op[d.pool_cell0 + (int64_t)s_qb * m];
+        d.record_algo = b.pool_algo[d.pool_cell0 + (int64_t)s_qb * m];
+    }
     if (!(d.g.flags & DABS_GA_RESTART)) return;
     const int h = d.g.merge_hamming;
     for (int c = tid; c < P * m; c += blockDim.x) {
@@ -440,6 +456,17 @@ __global__ __launch_bounds__(256) void k_pool_record(BatchDev b) {
 // Round counter; a cancelled round does not count.
 __global__ void k_round_end(unsigned long long *ctr) {
     if (threadIdx.x == 0 && !ctr[3]) ctr[2] += 1;
+}
+
+// Counters of problem p: out [STAT_WORDS + 2] = the counters, then the
+// record's operation and algorithm (-1 before the first record).
+__global__ void k_stats_out(BatchDev b, int p, int64_t *out) {
+    const ProbDesc &d = b.desc[p];
+    for (int w = threadIdx.x; w < STAT_WORDS; w += blockDim.x) out[w] = (int64_t)b.stats[(int64_t)p * STAT_WORDS + w];
+    if (threadIdx.x == 0) {
+        out[STAT_WORDS] = d.record_e == E_INF ? -1 : d.record_op;
+        out[STAT_WORDS + 1] = d.record_e == E_INF ? -1 : d.record_algo;
+    }
 }
 
 // Record of problem p: bits [nw], out [3] = (energy, restarts, rounds).
@@ -535,7 +562,7 @@ static void batched_free(dabs_batched *s) {
         if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
     void *ptrs[] = {s->d.desc, s->d.pool_bits, s->d.pool_e, s->d.pool_algo, s->d.pool_op, s->d.x, s->d.target,
                     s->d.best, s->d.e, s->d.best_e, s->d.ph, s->d.algo, s->d.op, s->d.inst_prob, s->d.ctr,
-                    s->d.record, s->items, s->item0, s->pool_list};
+                    s->d.record, s->d.stats, s->items, s->item0, s->pool_list};
     for (void *q : ptrs) (void)hipFree(q);
     (void)hipFree(s->mlp_cnt);
     (void)hipFree(s->mlp_feat);
@@ -587,7 +614,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         d.g = params[p];
         d.pool_cell0 = cells; d.pool_word0 = pwords; d.inst_word0 = iwords;
         d.target_e = INT64_MIN; d.hit = ~0ull;
-        d.rec_word0 = rwords; d.record_e = E_INF; d.epoch = 0;
+        d.rec_word0 = rwords; d.record_e = E_INF; d.epoch = 0; d.record_op = -1; d.record_algo = -1;
         rwords += d.nw;
         const int64_t pc = (int64_t)d.g.npools * d.g.capacity;
         inst += d.instances; cells += pc; pwords += pc * d.nw; iwords += (int64_t)d.instances * d.nw;
@@ -659,6 +686,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
               hipMalloc(&d.algo, 4 * (size_t)inst) == hipSuccess && hipMalloc(&d.op, 4 * (size_t)inst) == hipSuccess &&
               hipMalloc(&d.inst_prob, 4 * (size_t)inst) == hipSuccess &&
               hipMalloc(&d.ctr, 8 * 4) == hipSuccess && hipMalloc(&d.record, 8 * (size_t)rwords) == hipSuccess &&
+              hipMalloc(&d.stats, 8 * (size_t)STAT_WORDS * nprob) == hipSuccess &&
               hipMalloc(&s->items, sizeof(int2) * items.size()) == hipSuccess &&
               hipMalloc(&s->item0, sizeof(int) * nprob) == hipSuccess &&
               hipMalloc(&s->pool_list, sizeof(int2) * pl.size()) == hipSuccess;
@@ -687,7 +715,8 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
          hipMemsetAsync(d.e, 0, 8 * (size_t)inst, st) == hipSuccess &&
          hipMemsetAsync(d.ph, 0, 4 * (size_t)inst, st) == hipSuccess &&
          hipMemsetAsync(d.ctr, 0, 8 * 4, st) == hipSuccess &&
-         hipMemsetAsync(d.record, 0, 8 * (size_t)rwords, st) == hipSuccess;
+         hipMemsetAsync(d.record, 0, 8 * (size_t)rwords, st) == hipSuccess &&
+         hipMemsetAsync(d.stats, 0, 8 * (size_t)STAT_WORDS * nprob, st) == hipSuccess;
     for (int p = 0; p < nprob && ok; ++p) {
         const int64_t total = (int64_t)s->hdesc[p].g.npools * s->hdesc[p].g.capacity * s->hdesc[p].nw;
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
@@ -860,6 +889,13 @@ int dabs_batched_state(const dabs_batched *s, int32_t prob, uint64_t *x_dev, int
 int dabs_batched_record(const dabs_batched *s, int32_t prob, uint64_t *bits_dev, int64_t *out_dev, void *stream) {
     if (!s || prob < 0 || prob >= s->nprob) return dabs_fail(DABS_E_INVALID, "bad batch or problem index");
     hipLaunchKernelGGL(k_record_out, dim3(1), dim3(64), 0, (hipStream_t)stream, s->d, prob, bits_dev, out_dev);
+    HIP_OK(hipGetLastError());
+    return DABS_OK;
+}
+
+int dabs_batched_stats(const dabs_batched *s, int32_t prob, int64_t *out_dev, void *stream) {
+    if (!s || !out_dev || prob < 0 || prob >= s->nprob) return dabs_fail(DABS_E_INVALID, "bad batch, problem or output");
+    hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(64), 0, (hipStream_t)stream, s->d, prob, out_dev);
     HIP_OK(hipGetLastError());
     return DABS_OK;
 }
@@ -1100,6 +1136,11 @@ int dabs_solver_progress(const dabs_solver *s, int64_t *out_dev, void *stream) {
 int dabs_solver_record(const dabs_solver *s, uint64_t *bits_dev, int64_t *out_dev, void *stream) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
     return dabs_batched_record(s->b, 0, bits_dev, out_dev, stream);
+}
+
+int dabs_solver_stats(const dabs_solver *s, int64_t *out_dev, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_stats(s->b, 0, out_dev, stream);
 }
 
 int dabs_solver_set_cancel(dabs_solver *s, const volatile int32_t *flag_host) {

@@ -91,8 +91,12 @@ struct ProbDesc {
     int64_t rec_word0;             // first word of the problem's record vector
     int64_t record_e;              // energy of the record (E_INF before the first round)
     int32_t epoch;                 // restarts of merged pools so far
+    int32_t record_op, record_algo;// columns of the record's entry when it was last improved
     int32_t pad_;
 };
+// Per problem, the counters of the adaptive choice (Section IV-A): uses of
+// every operation and main algorithm, and the packets each put into a pool.
+enum { STAT_USE_OP = 0, STAT_USE_ALGO = 16, STAT_INS_OP = 24, STAT_INS_ALGO = 40, STAT_WORDS = 48 };
 
 struct BatchDev {
     ProbDesc *desc;
@@ -108,6 +112,7 @@ struct BatchDev {
     int32_t *need;                 // with pool_logits: per pool cell, read by a learned operation this round
     unsigned long long *ctr;       // [0] flips, [1] run start ticks, [2] round, [3] round cancelled
     uint64_t *record;              // per problem: best pooled vector of the run (kept across restarts)
+    unsigned long long *stats;     // per problem: STAT_WORDS counters
     const int *cancel;             // nullable: device view of the caller's pinned cancel flag
 };
 

@@ -39,16 +39,18 @@ def run_both(W, instances, rounds, **kw):
     ph = torch.zeros(instances, dtype=torch.int32, device=DEV)
     tot = torch.zeros(1, dtype=torch.int64, device=DEV)
     dabs.dabs_solver_state(s, x, e, ph, tot)
+    st = torch.zeros(dabs.DABS_STATS, dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_stats(s, st)
     torch.cuda.synchronize()
     got = dict(pool_bits=inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), pool_e=pe.cpu().numpy(),
                pool_algo=pa.cpu().numpy(), pool_op=po.cpu().numpy(),
                x=inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), e=e.cpu().numpy(),
-               ph=ph.cpu().numpy().view(np.uint32), flips=int(tot.item()))
+               ph=ph.cpu().numpy().view(np.uint32), flips=int(tot.item()), stats=st.cpu().numpy())
     return got, ref
 
 
 def assert_same(got, ref):
-    for k in ("pool_e", "pool_algo", "pool_op", "pool_bits", "x", "e", "ph"):
+    for k in ("pool_e", "pool_algo", "pool_op", "pool_bits", "x", "e", "ph", "stats"):
         assert np.array_equal(got[k], ref[k]), k
     assert got["flips"] == ref["flips"]
 

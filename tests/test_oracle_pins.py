@@ -266,3 +266,23 @@ def test_restart_on_merge():
         s = oracle.solve(W, g, I, r)
         assert s["best_e"] <= prev and E(W, s["best_bits"]) == s["best_e"]
         prev = s["best_e"]
+
+
+# ------------------------------------------------------------- bookkeeping
+def test_operation_and_algorithm_counters():
+    """The counters behind the tables of Section VI-D: every instance chooses
+    one operation and one main algorithm per round; a packet that enters a
+    pool counts once for its operation and once for its algorithm; the
+    record's columns are those of the pooled entry holding it."""
+    W = inputs.dense_qubo(60, -40, 40, 3)
+    I, R = 12, 4
+    r = oracle.solve(W, oracle.ga_params(T=6, Bn=60, tau=4, seed=2, capacity=5, npools=2), I, R)
+    st = r["stats"]
+    use_op, use_al, ins_op, ins_al = st[0:16], st[16:24], st[24:40], st[40:48]
+    assert use_op.sum() == I * R and use_al.sum() == I * R
+    n_ins = int((r["inserts"] >= 0).sum())
+    assert ins_op.sum() == n_ins and ins_al.sum() == n_ins
+    assert np.all(ins_op <= use_op) and np.all(ins_al <= use_al)
+    assert np.all(use_op[8:] == 0) and np.all(use_al[:2] == 0)       # only the enabled ones
+    q, k = np.argwhere(r["pool_e"] == r["best_e"])[0]
+    assert st[48] == r["pool_op"][q, k] and st[49] == r["pool_algo"][q, k]

@@ -54,7 +54,8 @@ int main(void) {
     int32_t pa[8], po[8], ins[5 * 6], nr;
     uint32_t pho[6];
     uint8_t bb[37];
-    if (orc_solve_ex(W, n, &g, inst, 5, pb, pe, pa, po, xo, eo, pho, ins, tg, pk, 1, NULL, NULL, bb, &be, &nr, rb) < 0)
+    int64_t stt[50];
+    if (orc_solve_ex(W, n, &g, inst, 5, pb, pe, pa, po, xo, eo, pho, ins, tg, pk, 1, NULL, NULL, bb, &be, &nr, rb, stt) < 0)
         return 3;
     free(W); free(pb); free(xo); free(tg);
     return 0;
