@@ -3,7 +3,17 @@ computes one at a time: after the first generational round every instance
 has run exactly one batch search from X = 0 towards a target drawn from the
 initial pools, so the oracle reproduces a sampled instance alone
 (first_target + batch_search) and its X, E and phase counter must equal the
-device's bit for bit."""
+device's bit for bit.
+
+The pools and the record after that round are checked through properties
+that hold at any size (Section III-C's insertion rule): every pool ascends
+in energy and holds no vector twice; every evaluated entry's energy is the
+oracle's E of its bits, and every unevaluated one is an initial entry of the
+same pool; a sampled packet (the oracle's BEST of that instance) strictly
+below its pool's final worst entry is pooled, since the worst energy never
+rises and an entry is evicted only as the worst; the record is the lowest
+pooled entry, with the oracle's energy, and no sampled packet lies below it;
+the adaptive choice counted one operation and one algorithm per instance."""
 import numpy as np
 import pytest
 
@@ -27,18 +37,68 @@ def og_params(g):
                             crossover_kind=g.crossover_kind, p_mutation=g.p_mutation, greedy_cap=g.greedy_cap)
 
 
+E_INF = np.iinfo(np.int64).max
+
+
 def check_sampled(W, g, x, e, ph, sample):
+    """Returns the oracle's packets {instance: (BEST bits, E(BEST))}."""
     n = W.shape[0]
     og = og_params(g)
+    packets = {}
     for i in sample:
         tgt, algo, _ = oracle.first_target(n, og, int(i))
         r = oracle.batch_search(W, algo, np.zeros(n, np.uint8), tgt, T=g.T, Bn=g.Bn, tau=g.tau, seed=g.seed,
                                 inst=int(i), ph=0, greedy_cap=g.greedy_cap)
         assert np.array_equal(x[i], r["x"]), i
         assert e[i] == r["e"] and ph[i] == r["ph"], i
+        packets[int(i)] = (r["best"], r["ebest"])
+    return packets
 
 
-def run_round1(W, g, instances):
+def check_pools(W, g, pool_bits, pool_e, record_bits, record_e, stats, instances, packets):
+    n = W.shape[0]
+    P, m = g.npools, g.capacity
+    init = oracle.solve(W, og_params(g), 1, 0)["pool_bits"]
+    for q in range(P):
+        assert np.all(pool_e[q][:-1] <= pool_e[q][1:]), q
+        seen = set()
+        for r in range(m):
+            key = np.packbits(pool_bits[q, r]).tobytes()
+            assert key not in seen, (q, r)
+            seen.add(key)
+            if pool_e[q, r] == E_INF:
+                assert any(np.array_equal(pool_bits[q, r], init[q, k]) for k in range(m)), (q, r)
+            else:
+                assert pool_e[q, r] == oracle.energy(W, pool_bits[q, r]), (q, r)
+    for i, (bb, eb) in packets.items():
+        q = i % P
+        assert eb >= record_e, i
+        if eb < pool_e[q, m - 1]:
+            rows = [r for r in range(m) if pool_e[q, r] == eb and np.array_equal(pool_bits[q, r], bb)]
+            assert len(rows) == 1, i
+    qb = int(np.argmin(pool_e[:, 0]))
+    assert record_e == pool_e[qb, 0] and np.array_equal(record_bits, pool_bits[qb, 0])
+    assert record_e == oracle.energy(W, record_bits)
+    assert stats[0:16].sum() == instances and stats[16:24].sum() == instances
+
+
+def device_pools(n, g, fetch_pools, fetch_record, fetch_stats):
+    P, m, nw = g.npools, g.capacity, (n + 63) // 64
+    bits = torch.zeros((P, m, nw), dtype=torch.int64, device=DEV)
+    pe = torch.zeros((P, m), dtype=torch.int64, device=DEV)
+    rb = torch.zeros(nw, dtype=torch.int64, device=DEV)
+    rec = torch.zeros(3, dtype=torch.int64, device=DEV)
+    st = torch.zeros(dabs.DABS_STATS, dtype=torch.int64, device=DEV)
+    fetch_pools(bits, pe)
+    fetch_record(rb, rec)
+    fetch_stats(st)
+    torch.cuda.synchronize()
+    return (inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), pe.cpu().numpy(),
+            inputs.unpack_bits(rb.cpu().numpy().view(np.uint64)[None], n)[0], int(rec[0].item()),
+            st.cpu().numpy())
+
+
+def run_round1(W, g, instances, smp):
     n = W.shape[0]
     p = dabs.dabs_problem_create(torch.from_numpy(W).to(DEV))
     s = dabs.dabs_solver_create(p, g, instances)
@@ -48,9 +108,11 @@ def run_round1(W, g, instances):
     e = torch.zeros(instances, dtype=torch.int64, device=DEV)
     ph = torch.zeros(instances, dtype=torch.int32, device=DEV)
     dabs.dabs_solver_state(s, x, e, ph)
-    torch.cuda.synchronize()
-    return (inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), e.cpu().numpy(),
-            ph.cpu().numpy().view(np.uint32))
+    pools = device_pools(n, g, lambda b, e_: dabs.dabs_solver_pools(s, b, e_),
+                         lambda b, o: dabs.dabs_solver_record(s, b, o), lambda o: dabs.dabs_solver_stats(s, o))
+    packets = check_sampled(W, g, inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), e.cpu().numpy(),
+                            ph.cpu().numpy().view(np.uint32), smp)
+    check_pools(W, g, *pools, instances, packets)
 
 
 def sample(instances, seed, k=4):
@@ -61,8 +123,7 @@ def sample(instances, seed, k=4):
 def test_maxcut800_4096_instances():
     W, _, _ = inputs.maxcut_instance(800, 0.06, seed=0)
     g = dabs.ga_params(T=80, Bn=8000, tau=8, seed=0, capacity=100, npools=8, greedy_cap=CAP)
-    x, e, ph = run_round1(W, g, 4096)
-    check_sampled(W, g, x, e, ph, sample(4096, 1))
+    run_round1(W, g, 4096, sample(4096, 1))
 
 
 def test_tsp32_8192_instances():
@@ -72,15 +133,13 @@ def test_tsp32_8192_instances():
     assert W.shape == (1024, 1024) and W.dtype == np.int32
     g = dabs.ga_params(T=102, Bn=1024, tau=8, seed=0, capacity=100, npools=8, crossover_kind=1,
                        p_mutation=oracle.P_ONE_PERCENT, greedy_cap=CAP)
-    x, e, ph = run_round1(W, g, 8192)
-    check_sampled(W, g, x, e, ph, sample(8192, 2))
+    run_round1(W, g, 8192, sample(8192, 2))
 
 
 def test_dense2048_1024_instances():
     W = inputs.dense_qubo(2048, -1000, 1000, 0)
     g = dabs.ga_params(T=205, Bn=2048, tau=8, seed=0, capacity=100, npools=8, greedy_cap=CAP)
-    x, e, ph = run_round1(W, g, 1024)
-    check_sampled(W, g, x, e, ph, sample(1024, 3, 2))
+    run_round1(W, g, 1024, sample(1024, 3, 2))
 
 
 def test_batched_256_problems_graph_round():
@@ -104,6 +163,9 @@ def test_batched_256_problems_graph_round():
         e = torch.zeros(inst, dtype=torch.int64, device=DEV)
         ph = torch.zeros(inst, dtype=torch.int32, device=DEV)
         dabs.dabs_batched_state(b, q, x, e, ph)
-        torch.cuda.synchronize()
-        check_sampled(W, params[q], inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), e.cpu().numpy(),
-                      ph.cpu().numpy().view(np.uint32), [0, 17, inst - 1])
+        pools = device_pools(n, params[q], lambda b_, e_: dabs.dabs_batched_pools(b, q, b_, e_),
+                             lambda b_, o: dabs.dabs_batched_record(b, q, b_, o),
+                             lambda o: dabs.dabs_batched_stats(b, q, o))
+        packets = check_sampled(W, params[q], inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n),
+                                e.cpu().numpy(), ph.cpu().numpy().view(np.uint32), [0, 1, 17, inst - 1])
+        check_pools(W, params[q], *pools, inst, packets)

@@ -115,6 +115,23 @@ def test_search_parity(rule, n, wt):
     compare(g, o, cap)
 
 
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("n,wt", [(4096, np.int16), (4095, np.int16), (2048, np.int32), (1985, np.int32)])
+def test_search_parity_max_sizes(rule, n, wt):
+    """The largest dense problems each weight type serves (eight slots: the
+    two-half register vectors of int16, the int32 key shift at its widest)
+    and ragged sizes one slot piece below them."""
+    assert n <= dabs.dabs_max_n(dabs.DABS_W_I16 if wt == np.int16 else dabs.DABS_W_I32)
+    W = inputs.dense_qubo(n, -1000, 1000, 31 + n, dtype=wt)
+    p = load(W)
+    X0 = inputs.random_bits(3, n, 5 * n)
+    tg = inputs.random_bits(3, n, 6 * n)
+    cap = 4 * n + 64
+    kw = dict(T=150, tau=8 if rule != oracle.TWONEIGHBOR else 0, seed=777, phase=2, inst0=9, trace_cap=cap,
+              targets=tg if rule == oracle.STRAIGHT else None)
+    compare(gpu_search(p, rule, X0, **kw), oracle_search(W, rule, X0, **kw), cap)
+
+
 @pytest.mark.parametrize("n,wt", [(24, np.int16), (800, np.int16), (300, np.int32)])
 def test_search_parity_maxcut_and_small_tau(n, wt):
     """Max-cut W (many equal deltas: exercises the lowest-index tie rule)."""
@@ -157,7 +174,8 @@ def test_c1_full_size():
     assert g["ebest"].min() == opt
 
 
-@pytest.mark.parametrize("n,wt", [(24, np.int16), (200, np.int16), (800, np.int16), (300, np.int32)])
+@pytest.mark.parametrize("n,wt", [(24, np.int16), (200, np.int16), (800, np.int16), (300, np.int32),
+                                  (4096, np.int16), (2048, np.int32)])
 def test_batch_search_parity(n, wt):
     W = inputs.dense_qubo(n, -200, 200, 77 + n, dtype=wt)
     p = load(W)

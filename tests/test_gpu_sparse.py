@@ -108,6 +108,44 @@ def test_sparse_search_parity(rule, n, p, kind):
         assert np.array_equal(delta[c].cpu().numpy().astype(np.int64), r["delta"]), c
 
 
+@pytest.mark.parametrize("n", [15360, 15001])
+def test_sparse_search_parity_max_size(n):
+    """The largest sparse problem the walker serves (60 pieces per lane) and a
+    ragged size below it, average degree 12, every rule; the oracle runs on
+    the same W stored dense (int32)."""
+    assert n <= dabs.dabs_max_n(dabs.DABS_W_SPARSE)
+    W = random_sparse(n, 12.0 / n, -50, 50, 3 * n).astype(np.int32)
+    pr = sparse_problem(W)
+    cnt = 2
+    X0 = inputs.random_bits(cnt, n, 21 + n)
+    targets = inputs.random_bits(cnt, n, 22 + n)
+    cap = n + 300
+    for rule in RULES:
+        print("sparse search n=%d rule %d" % (n, rule), flush=True)
+        x = dev(inputs.pack_bits(X0).view(np.int64))
+        best = torch.zeros_like(x)
+        be = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+        e = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+        delta = torch.zeros((cnt, n), dtype=torch.int32, device=DEV)
+        trace = torch.zeros((cnt, cap), dtype=torch.int32, device=DEV)
+        flips = torch.zeros(cnt, dtype=torch.int32, device=DEV)
+        sp = dabs.dabs_search_params(rule=rule, T=300, tau=8, greedy_cap=CAP, seed=5, phase=0, inst0=1)
+        dabs.dabs_search(pr, sp, x, dev(inputs.pack_bits(targets).view(np.int64)), best, be, e, delta, trace,
+                         flips)
+        torch.cuda.synchronize()
+        gx = inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n)
+        gb = inputs.unpack_bits(best.cpu().numpy().view(np.uint64), n)
+        for c in range(cnt):
+            r = oracle.search(W, rule, X0[c], T=300, tau=8, seed=5, inst=1 + c, ph=0, target=targets[c],
+                              greedy_cap=CAP, trace_cap=cap)
+            f = r["flips"]
+            assert int(flips[c]) == f, (rule, c)
+            assert np.array_equal(trace[c].cpu().numpy()[:min(f, cap)], r["trace"][:min(f, cap)]), (rule, c)
+            assert int(e[c]) == r["e"] and int(be[c]) == r["ebest"], (rule, c)
+            assert np.array_equal(gx[c], r["x"]) and np.array_equal(gb[c], r["best"]), (rule, c)
+            assert np.array_equal(delta[c].cpu().numpy().astype(np.int64), r["delta"]), (rule, c)
+
+
 @pytest.mark.parametrize("n,p,kind", [(300, 0.05, "rand"), (800, 0.06, "maxcut")])
 def test_sparse_batch_search_parity(n, p, kind):
     W = case_W(n, p, kind)
