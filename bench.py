@@ -47,7 +47,8 @@ def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2207_03069_amd", "csrc")
-    for f in [os.path.join(csrc, x) for x in ("dabs_walk.hip", "dabs_walker.h", "dabs_device.h", "dabs_internal.h")]:
+    for f in [os.path.join(csrc, x) for x in ("dabs_walk.hip", "dabs_walker.h", "dabs_sparse.h", "dabs_device.h",
+                                              "dabs_internal.h")] + [os.path.join(ROOT, "include", "dabs.h")]:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
@@ -334,8 +335,7 @@ def tsp_quality(dev, rounds=8, ncity=32):
     return {"workload": "TSP 32 cities -> one-hot QUBO n=1024, int32 W, A=2*max d=%d; 8192 instances, "
                         "8 pools x 100, two-point crossover, 1%% mutation, s=0.1 b=1" % A,
             "rounds": rounds, "wall_s": wall, "flips": int(tot.item()), "flips_per_s": int(tot.item()) / wall,
-            "best_energy": best_e,
-        "adaptive_choice": adaptive, "best_is_tour": tour_ok, "tour_length": length,
+            "best_energy": best_e, "best_is_tour": tour_ok, "tour_length": length,
             "energy_check": (best_e == 2 * length - 2 * ncity * A) if tour_ok else None,
             "nearest_neighbour_length": nn}
 
@@ -524,6 +524,69 @@ def small_n(dev, lds_peak):
                                     "lds_peak_GB_per_s": lds_peak}}
 
 
+RULE_NAMES = ["Greedy", "Straight", "MaxMin", "CyclicMin", "RandomMin", "PositiveMin", "TwoNeighbor", "TabuGreedy"]
+
+
+def rule_costs(W, dev, cnt=4096, T=2000):
+    """Cost of each search rule alone on the main workload's W: one
+    dabs_search launch per rule (Section III-A), 4096 instances from seeded
+    random X (the walk from X = 0 to X is part of each launch), T = 2000
+    iterations (Greedy: to a local minimum; Straight: to a seeded random
+    target; TwoNeighbor: its 2n - 1 flips), tau = 8.  HIP events on the
+    launch's stream."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    n = W.shape[0]
+    p = dabs.dabs_problem_create(torch.from_numpy(W).to(dev))
+    X0 = torch.from_numpy(inputs.pack_bits(inputs.random_bits(cnt, n, 1)).view(np.int64)).to(dev)
+    tg = torch.from_numpy(inputs.pack_bits(inputs.random_bits(cnt, n, 2)).view(np.int64)).to(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    for rule, name in enumerate(RULE_NAMES):
+        x = X0.clone()
+        best = torch.zeros_like(x)
+        be = torch.zeros(cnt, dtype=torch.int64, device=dev)
+        e = torch.zeros(cnt, dtype=torch.int64, device=dev)
+        fl = torch.zeros(cnt, dtype=torch.int32, device=dev)
+        sp = dabs.dabs_search_params(rule=rule, T=T, tau=TAU, greedy_cap=100000, seed=1, phase=0, inst0=0)
+        torch.cuda.synchronize()
+        ev[0].record()
+        dabs.dabs_search(p, sp, x, tg, best, be, e, None, None, fl)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        f = int(fl.sum().item())
+        out[name] = {"flips": f, "ms": ms, "flips_per_s": f / (ms / 1e3),
+                     "us_per_flip_per_wave": ms * 1e3 / (f / cnt)}
+    return {"workload": "maxcut G(800,0.06) int16, %d instances, T=%d, tau=%d, one launch per rule" % (cnt, T, TAU),
+            "rules": out}
+
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_walk_items_maxcut800_counters.json")
+
+
+def measured_issue(flips_per_launch, avg_launch_ms):
+    """VALU / SALU instructions per flip of the batch-search kernel from the
+    committed rocprofv3 counter summary (None when the kernels changed
+    since), and the VALU issue time they imply per SIMD at 2.4 GHz."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    valu, salu = t["valu_per_flip"], t["salu_per_flip"]
+    simds = 256 * 4
+    # a wave64 VALU instruction occupies its SIMD's 16 lanes for 4 cycles
+    busy = valu * flips_per_launch / simds * 4 / (avg_launch_ms * 1e-3 * 2.4e9)
+    return {"valu_per_flip": valu, "salu_per_flip": salu, "vmem_per_flip": t.get("vmem_per_flip"),
+            "algorithmic_lane_ops_per_flip": 2 * N_BITS // 64,
+            "valu_busy_at_2p4GHz": busy,
+            "note": "instructions per flip per wavefront (SQ_INSTS_VALU, SQ_INSTS_SALU over flips); valu_busy = "
+                    "VALU instructions x 4 cycles per SIMD over the launch time"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,10 +599,16 @@ def main():
     ap.add_argument("--no-tsp", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-rules", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 256 MiB device copy")
+    ap.add_argument("--rule-costs", action="store_true", help="only time each search rule alone")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.rule_costs:
+        import torch
+        print(json.dumps(rule_costs(workload()[0], torch.device("cuda:0"))))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -615,6 +684,7 @@ def main():
                 "avg_launch_ms": walk_ms / max(launches, 1),
                 "peaks_measured": peaks,
                 "hbm_frac": achieved / peaks["hbm"]["GB/s"],
+                "issue": measured_issue(walk_flips / max(launches, 1), walk_ms / max(launches, 1)),
                 "alu": {"achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                         "unit": "Tops/s (int32 lane-ops: 2n per flip, Eq. (4) update + Steps 1-2 comparison)",
                         "frac": achieved_ops / VALU_PEAK_OPS},
@@ -656,6 +726,10 @@ def main():
                                             for x in per_seed])),
                "per_seed": per_seed,
                "note": "device clock (100 MHz) from the arming call to the first E(BEST) <= target"}
+    rules = None
+    if not args.no_rules:
+        print("bench: each rule alone ...", file=sys.stderr, flush=True)
+        rules = rule_costs(W, dev)
     sparse = None
     if not args.no_sparse:
         print("bench: sparse workloads ...", file=sys.stderr, flush=True)
@@ -692,10 +766,12 @@ def main():
                    "n": N_BITS, "instances": INSTANCES, "rounds_per_step": ROUNDS_PER_STEP, "T": T, "Bn": Bn,
                    "tau": TAU, "npools": NPOOLS, "capacity": CAPACITY, "flips_per_step": flips / args.steps},
         "best_energy": best_e,
+        "adaptive_choice": adaptive,
         "time_to_target": tts,
         "time_to_target_learned_vs_plain": learned,
         "time_to_target_batched_vs_single": batched,
         "tsp": tsp,
+        "rule_costs": rules,
         "sparse": sparse,
         "small_n_lds_rows": small,
         "roofline": roofline,
