@@ -3,18 +3,23 @@
 // training (binary cross-entropy, Adam) and the two genetic operations that
 // consume the logits (MLP-seed, MLP-mutate).
 //
-// Matrix products run on the matrix cores: v_mfma_f32_16x16x16_bf16 with
-// bfloat16 operands (round to nearest even) and float32 accumulation.
-// Operand layouts of that instruction, lane l = 0..63, g = l / 16, c = l % 16:
-//   A[i][k] (16 x 16): lane i + 16 floor(k/4), element k mod 4
-//   B[k][j] (16 x 16): lane j + 16 floor(k/4), element k mod 4
+// Matrix products run on the matrix cores with bfloat16 operands (round to
+// nearest even) and float32 accumulation.  Lane l = 0..63, g = l / 16,
+// c = l % 16.  The forward pass uses gfx950's v_mfma_f32_16x16x32_bf16:
+//   A[i][k] (16 x 32): lane i + 16 floor(k/8), element k mod 8
+//   B[k][j] (32 x 16): lane j + 16 floor(k/8), element k mod 8
 //   D[i][j] (16 x 16): lane j + 16 floor(i/4), element i mod 4
-// Activations are kept transposed (hidden unit x sample): a layer's output
-// tile D (16 units x 16 samples) is then, element for element, the B operand
-// of the next layer's 16-unit slice of its reduction, so the forward pass
-// needs no data movement between layers.  The weight gradients reduce over
-// samples and need the transposed tiles; each wavefront stages them through
-// its own 6.3 KB of LDS.
+// Activations are kept transposed (hidden unit x sample).  A layer's output
+// tiles D (16 units x 16 samples) hold in lane (g, c) the units 16t + 4g + e
+// of sample c; the next layer's 32-deep reduction block u takes the
+// elements of tiles 2u and 2u + 1 of a lane, in that order, as its B operand
+// (reduction index 8g + e' = unit 16 (2u + e'/4) + 4g + e' mod 4), and
+// the weights are loaded in the same order, so the forward pass needs no
+// data movement between layers.  The biases start the accumulators.
+// The backward products use v_mfma_f32_16x16x16_bf16 (same D layout;
+// A and B with element k mod 4 in lane i (j) + 16 floor(k/4)).  The weight
+// gradients reduce over samples and need the transposed tiles; each
+// wavefront stages them through its own 6.3 KB of LDS.
 #include <math.h>
 #include <string.h>
 
@@ -33,7 +38,12 @@
 namespace dabs {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 hbf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 hbf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int NF = 8, HID = 64;
 constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 4736, OFF_B3 = 4800;
@@ -48,9 +58,19 @@ __device__ __forceinline__ short to_bf16(float f) {
     return (short)(u >> 16);
 }
 __device__ __forceinline__ float bf16_val(short b) { return __uint_as_float((uint32_t)(uint16_t)b << 16); }
+// two float32 -> packed bfloat16 (a low, b high), round to nearest even: one
+// v_cvt_pk_bf16_f32, the same values as to_bf16 for finite inputs
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, hbf16x2));
+}
 
 __device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(hbf16x8, a), __builtin_bit_cast(hbf16x8, b),
+                                                   c, 0, 0, 0);
 }
 
 // four consecutive bfloat16 values (8-byte aligned)
@@ -61,97 +81,112 @@ __device__ __forceinline__ bf16x4 ld4(const short *p) {
     v.z = (short)(u.y & 0xFFFF); v.w = (short)(u.y >> 16);
     return v;
 }
+__device__ __forceinline__ bf16x8 cat8(bf16x4 a, bf16x4 b) {
+    return bf16x8{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+// hidden unit of reduction index 8g + e' in 32-deep block u (see above)
+__device__ __forceinline__ int unit_of(int u, int g, int e) { return 16 * (2 * u + (e >> 2)) + 4 * g + (e & 3); }
 
 // Weights of one wavefront in matrix-core operand form.
 struct Net {
-    bf16x4 a1[4];          // W1 (64 x 16, features 8..15 zero), one tile per 16 hidden units
-    bf16x4 a2[4][4];       // W2 tiles [out][in]
-    bf16x4 a3[4];          // W3 as row 0 of a 16 x 64 matrix
-    float b1[4][4], b2[4][4], w3[4][4];   // per lane: unit 16 t + 4 g + e
+    bf16x8 f1[4];          // W1 tile t (units 16 t + c, features 0..7 in lane group 0), 16x16x32 A operand
+    bf16x8 f2[4][2];       // W2 tile [out t][block u], 16x16x32 A operand
+    bf16x8 f3[2];          // W3 as row 0 of a 16 x 64 matrix, blocks u
+    f32x4 c1[4], c2[4];    // biases of units 16 t + 4 g + e: the accumulators' start
+    float w3[4][4];        // per lane: unit 16 t + 4 g + e
     float b3;
 
     __device__ void load(const short *__restrict__ wbf, const float *__restrict__ par, int lane) {
         const int g = lane >> 4, c = lane & 15;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            a1[t] = g < 2 ? ld4(wbf + OFF_W1 + (16 * t + c) * NF + 4 * g) : bf16x4{0, 0, 0, 0};
+            f1[t] = g == 0 ? cat8(ld4(wbf + OFF_W1 + (16 * t + c) * NF), ld4(wbf + OFF_W1 + (16 * t + c) * NF + 4))
+                           : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) a2[t][kt] = ld4(wbf + OFF_W2 + (16 * t + c) * HID + 16 * kt + 4 * g);
-            a3[t] = c == 0 ? ld4(wbf + OFF_W3 + 16 * t + 4 * g) : bf16x4{0, 0, 0, 0};
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) f2[t][u][e] = wbf[OFF_W2 + (16 * t + c) * HID + unit_of(u, g, e)];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int u = 16 * t + 4 * g + e;
-                b1[t][e] = par[OFF_B1 + u];
-                b2[t][e] = par[OFF_B2 + u];
+                c1[t][e] = par[OFF_B1 + u];
+                c2[t][e] = par[OFF_B2 + u];
                 w3[t][e] = bf16_val(wbf[OFF_W3 + u]);
             }
         }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f3[u][e] = c == 0 ? wbf[OFF_W3 + unit_of(u, g, e)] : (short)0;
         b3 = par[OFF_B3];
     }
 };
 
-// Feature operand of the 16 samples s0 .. s0+15: lane (g, c) holds features
-// 4g .. 4g+3 of sample s0 + c (zero for g >= 2 and past the end).
-__device__ __forceinline__ bf16x4 load_feat(const short *__restrict__ feat, int64_t N, int64_t s0, int lane) {
+// Feature operand of the 16 samples s0 .. s0+15: lane (0, c) holds the 8
+// features of sample s0 + c (zero past the end); the other lane groups zero.
+__device__ __forceinline__ bf16x8 load_feat(const short *__restrict__ feat, int64_t N, int64_t s0, int lane) {
     const int g = lane >> 4, c = lane & 15;
-    if (g >= 2 || s0 + c >= N) return bf16x4{0, 0, 0, 0};
-    const uint2 v = *(const uint2 *)(feat + (s0 + c) * NF + 4 * g);
-    bf16x4 r;
-    r.x = (short)(v.x & 0xFFFF); r.y = (short)(v.x >> 16);
-    r.z = (short)(v.y & 0xFFFF); r.w = (short)(v.y >> 16);
-    return r;
+    if (g != 0 || s0 + c >= N) return bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    const uint4 v = *(const uint4 *)(feat + (s0 + c) * NF);
+    return __builtin_bit_cast(bf16x8, v);
 }
-
-// Forward pass of one tile.  h1/h2: bfloat16 activations in B-operand form;
-// m1/m2: bit (4t + e) set when the pre-activation of unit 16t + 4g + e is > 0.
-// Returns the logit (valid in lanes 0..15, sample s0 + lane).
-__device__ __forceinline__ float fwd_tile(const Net &w, bf16x4 x, bf16x4 (&h1)[4], bf16x4 (&h2)[4], uint32_t &m1,
+// Forward pass of one tile.  h1/h2: bfloat16 activations in the D layout
+// (lane (g, c): units 16t + 4g + e of sample c); m1/m2: bit (4t + e) set when
+// the pre-activation of unit 16t + 4g + e is > 0.  Returns the logit (valid
+// in lanes 0..15, sample s0 + lane).
+// ReLU on the bit pattern: a float with the sign bit set (negative, -0)
+// is a negative int32 and becomes +0, one integer max per value
+__device__ __forceinline__ float relu(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
+__device__ __forceinline__ bf16x4 relu_bf16(f32x4 d) {
+    const u32x2 v = {pk_bf16(relu(d[0]), relu(d[1])), pk_bf16(relu(d[2]), relu(d[3]))};
+    return __builtin_bit_cast(bf16x4, v);
+}
+__device__ __forceinline__ uint32_t pos_bits(f32x4 d, int t) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m |= (d[e] > 0.f ? 1u : 0u) << (4 * t + e);
+    return m;
+}
+__device__ __forceinline__ float fwd_tile(const Net &w, bf16x8 x, bf16x4 (&h1)[4], bf16x4 (&h2)[4], uint32_t &m1,
                                           uint32_t &m2) {
-    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     m1 = 0;
     m2 = 0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const f32x4 d = mma(w.a1[t], x, zero);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float z = d[e] + w.b1[t][e];
-            m1 |= (z > 0.f ? 1u : 0u) << (4 * t + e);
-            h1[t][e] = to_bf16(z > 0.f ? z : 0.f);
-        }
+        const f32x4 d = mma32(w.f1[t], x, w.c1[t]);
+        m1 |= pos_bits(d, t);
+        h1[t] = relu_bf16(d);
     }
+    const bf16x8 b0 = cat8(h1[0], h1[1]), b1 = cat8(h1[2], h1[3]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 d = zero;
-#pragma unroll
-        for (int kt = 0; kt < 4; ++kt) d = mma(w.a2[t][kt], h1[kt], d);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float z = d[e] + w.b2[t][e];
-            m2 |= (z > 0.f ? 1u : 0u) << (4 * t + e);
-            h2[t][e] = to_bf16(z > 0.f ? z : 0.f);
-        }
+        const f32x4 d = mma32(w.f2[t][1], b1, mma32(w.f2[t][0], b0, w.c2[t]));
+        m2 |= pos_bits(d, t);
+        h2[t] = relu_bf16(d);
     }
-    f32x4 d = zero;
-#pragma unroll
-    for (int kt = 0; kt < 4; ++kt) d = mma(w.a3[kt], h2[kt], d);
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    const f32x4 d = mma32(w.f3[1], cat8(h2[2], h2[3]), mma32(w.f3[0], cat8(h2[0], h2[1]), zero));
     return d[0] + w.b3;
 }
 
-// Logits of N samples; one wavefront per workgroup, tiles of 16 samples
-// strided over the grid.
-__global__ __launch_bounds__(64) void k_mlp_fwd(const short *__restrict__ wbf, const float *__restrict__ par,
-                                                const short *__restrict__ feat, int64_t N, float *__restrict__ out) {
+// Logits of N samples; one wavefront per workgroup, pairs of 16-sample
+// tiles (t, t + gridDim.x) strided over the grid.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_fwd(
+    const short *__restrict__ wbf, const float *__restrict__ par, const short *__restrict__ feat, int64_t N,
+    float *__restrict__ out) {
     const int lane = (int)threadIdx.x;
     Net w;
     w.load(wbf, par, lane);
     const int64_t tiles = (N + 15) / 16;
-    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const int64_t s0 = t * 16;
-        bf16x4 h1[4], h2[4];
-        uint32_t m1, m2;
-        const float z = fwd_tile(w, load_feat(feat, N, s0, lane), h1, h2, m1, m2);
-        if (lane < 16 && s0 + lane < N) out[s0 + lane] = z;
+    for (int64_t t = blockIdx.x; t < tiles; t += 2 * (int64_t)gridDim.x) {
+        const int64_t s0 = t * 16, s1 = (t + gridDim.x) * 16;   // s1 may lie past N: its samples are zero
+        bf16x4 h1[4], h2[4], k1[4], k2[4];
+        uint32_t m1, m2, n1, n2;
+        const bf16x8 x0 = load_feat(feat, N, s0, lane), x1 = load_feat(feat, N, s1, lane);
+        const float z0 = fwd_tile(w, x0, h1, h2, m1, m2);
+        const float z1 = fwd_tile(w, x1, k1, k2, n1, n2);
+        if (lane < 16 && s0 + lane < N) out[s0 + lane] = z0;
+        if (lane < 16 && s1 + lane < N) out[s1 + lane] = z1;
     }
 }
 
@@ -189,7 +224,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
     const int64_t tiles = (N + 15) / 16;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const int64_t s0 = t * 16;
-        const bf16x4 x = load_feat(feat, N, s0, lane);
+        const bf16x8 x = load_feat(feat, N, s0, lane);
         bf16x4 h1[4], h2[4];
         uint32_t m1, m2;
         const float z = fwd_tile(w, x, h1, h2, m1, m2);
@@ -205,14 +240,17 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
         const float dzc = __shfl(dz, c, 64);
         bf16x4 d2[4], d1[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) {
+            float d[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 gW3[u][e] += dzc * bf16_val(h2[u][e]);
-                const float d = ((m2 >> (4 * u + e)) & 1) ? w.w3[u][e] * dzc : 0.f;
-                gB2[u][e] += d;
-                d2[u][e] = to_bf16(d);
+                d[e] = ((m2 >> (4 * u + e)) & 1) ? w.w3[u][e] * dzc : 0.f;
+                gB2[u][e] += d[e];
             }
+            const u32x2 v = {pk_bf16(d[0], d[1]), pk_bf16(d[2], d[3])};
+            d2[u] = __builtin_bit_cast(bf16x4, v);
+        }
         // dH1 = W2^T dA2: A operand W2^T[16 it + c][16 ot + 4g + e] from global (L1/L2 resident)
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
@@ -224,12 +262,14 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
                 for (int e = 0; e < 4; ++e) a[e] = wbf[OFF_W2 + (16 * ot + 4 * g + e) * HID + 16 * it + c];
                 acc = mma(a, d2[ot], acc);
             }
+            float d[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float d = ((m1 >> (4 * it + e)) & 1) ? acc[e] : 0.f;
-                gB1[it][e] += d;
-                d1[it][e] = to_bf16(d);
+                d[e] = ((m1 >> (4 * it + e)) & 1) ? acc[e] : 0.f;
+                gB1[it][e] += d[e];
             }
+            const u32x2 v = {pk_bf16(d[0], d[1]), pk_bf16(d[2], d[3])};
+            d1[it] = __builtin_bit_cast(bf16x4, v);
         }
         // stage (unit x sample) tiles for the reductions over samples
 #pragma unroll
@@ -240,9 +280,9 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
                 sH1[16 * u + 4 * g + e][c] = h1[u][e];
                 sA1[16 * u + 4 * g + e][c] = d1[u][e];
             }
-        if (g < 2)
+        if (g == 0)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) sF[4 * g + e][c] = x[e];
+            for (int e = 0; e < NF; ++e) sF[e][c] = x[e];
         __syncthreads();
         // dW2[out][in] += sum_s dA2[out][s] a1[in][s];  dW1[out][f] += sum_s dA1[out][s] F[f][s]
         bf16x4 bh[4];
