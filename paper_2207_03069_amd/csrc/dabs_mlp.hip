@@ -205,7 +205,15 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
                                                  const short *__restrict__ feat, const uint8_t *__restrict__ label,
                                                  int64_t N, float invN, float *__restrict__ part) {
     __shared__ __attribute__((aligned(16))) short sA2[HID][16], sH1[HID][16], sA1[HID][16], sF[NF][16];
+    // W2 transposed with its output units in the 16x16x32 reduction order:
+    // sW2P[in][32 kb + 8 g + e] = W2[unit_of(kb, g, e)][in]
+    __shared__ __attribute__((aligned(16))) short sW2P[HID][HID];
     const int lane = (int)threadIdx.x, g = lane >> 4, c = lane & 15;
+    for (int i = lane; i < HID * HID; i += WAVE) {
+        const int in = i / HID, k = i % HID;
+        sW2P[in][k] = wbf[OFF_W2 + unit_of(k >> 5, (k >> 3) & 3, k & 7) * HID + in];
+    }
+    __syncthreads();
     Net w;
     w.load(wbf, par, lane);
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
@@ -222,16 +230,23 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
     }
     float gB3 = 0.f, lsum = 0.f;
     const int64_t tiles = (N + 15) / 16;
+    // the next tile's features and labels load while this tile is worked on
+    auto load_label = [&](int64_t s) { return lane < 16 && s + lane < N ? label[s + lane] : (uint8_t)0; };
+    bf16x8 x_next = load_feat(feat, N, (int64_t)blockIdx.x * 16, lane);
+    uint8_t y_next = load_label((int64_t)blockIdx.x * 16);
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const int64_t s0 = t * 16;
-        const bf16x8 x = load_feat(feat, N, s0, lane);
+        const bf16x8 x = x_next;
+        const uint8_t ylab = y_next;
+        x_next = load_feat(feat, N, s0 + 16 * (int64_t)gridDim.x, lane);
+        y_next = load_label(s0 + 16 * (int64_t)gridDim.x);
         bf16x4 h1[4], h2[4];
         uint32_t m1, m2;
         const float z = fwd_tile(w, x, h1, h2, m1, m2);
         // dL/dz of sample s0 + lane (lanes 0..15), then broadcast by sample
         float dz = 0.f;
         if (lane < 16 && s0 + lane < N) {
-            const float y = label[s0 + lane] ? 1.f : 0.f;
+            const float y = ylab ? 1.f : 0.f;
             const float s = 1.f / (1.f + expf(-z));
             dz = (s - y) * invN;
             lsum += fmaxf(z, 0.f) - y * z + log1pf(expf(-fabsf(z)));
@@ -251,17 +266,14 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const short *__restrict__ wbf, 
             const u32x2 v = {pk_bf16(d[0], d[1]), pk_bf16(d[2], d[3])};
             d2[u] = __builtin_bit_cast(bf16x4, v);
         }
-        // dH1 = W2^T dA2: A operand W2^T[16 it + c][16 ot + 4g + e] from global (L1/L2 resident)
+        // dH1 = W2^T dA2 on the 16x16x32 products: B = the dA2 tiles 2kb, 2kb + 1
+        // of a lane concatenated, A = W2^T rows from LDS in the same order
+        const bf16x8 b0 = cat8(d2[0], d2[1]), b1 = cat8(d2[2], d2[3]);
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
-            f32x4 acc = zero;
-#pragma unroll
-            for (int ot = 0; ot < 4; ++ot) {
-                bf16x4 a;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) a[e] = wbf[OFF_W2 + (16 * ot + 4 * g + e) * HID + 16 * it + c];
-                acc = mma(a, d2[ot], acc);
-            }
+            const bf16x8 a0 = *(const bf16x8 *)&sW2P[16 * it + c][8 * g];
+            const bf16x8 a1 = *(const bf16x8 *)&sW2P[16 * it + c][32 + 8 * g];
+            const f32x4 acc = mma32(a1, b1, mma32(a0, b0, zero));
             float d[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
