@@ -177,14 +177,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int lane = (int)threadIdx.x;
     Net w;
     w.load(wbf, par, lane);
-    const int64_t tiles = (N + 15) / 16;
-    for (int64_t t = blockIdx.x; t < tiles; t += 2 * (int64_t)gridDim.x) {
-        const int64_t s0 = t * 16, s1 = (t + gridDim.x) * 16;   // s1 may lie past N: its samples are zero
+    const int64_t tiles = (N + 15) / 16, G = gridDim.x;
+    // the next pair's features load while this pair is worked on
+    bf16x8 n0 = load_feat(feat, N, (int64_t)blockIdx.x * 16, lane), n1 = load_feat(feat, N, (blockIdx.x + G) * 16, lane);
+    for (int64_t t = blockIdx.x; t < tiles; t += 2 * G) {
+        const int64_t s0 = t * 16, s1 = (t + G) * 16;   // s1 may lie past N: its samples are zero
         bf16x4 h1[4], h2[4], k1[4], k2[4];
-        uint32_t m1, m2, n1, n2;
-        const bf16x8 x0 = load_feat(feat, N, s0, lane), x1 = load_feat(feat, N, s1, lane);
+        uint32_t m1, m2, q1, q2;
+        const bf16x8 x0 = n0, x1 = n1;
+        n0 = load_feat(feat, N, s0 + 32 * G, lane);
+        n1 = load_feat(feat, N, s1 + 32 * G, lane);
         const float z0 = fwd_tile(w, x0, h1, h2, m1, m2);
-        const float z1 = fwd_tile(w, x1, k1, k2, n1, n2);
+        const float z1 = fwd_tile(w, x1, k1, k2, q1, q2);
         if (lane < 16 && s0 + lane < N) out[s0 + lane] = z0;
         if (lane < 16 && s1 + lane < N) out[s1 + lane] = z1;
     }
