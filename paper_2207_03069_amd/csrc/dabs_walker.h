@@ -82,6 +82,11 @@ struct RegVec {
     }
 };
 
+template <bool NARROW> struct MaskOf { typedef uint64_t type; };
+template <> struct MaskOf<true> { typedef uint32_t type; };
+__device__ __forceinline__ uint32_t lane_mask(uint32_t v, int l) { return (uint32_t)readlane((int)v, l); }
+__device__ __forceinline__ uint64_t lane_mask(uint64_t v, int l) { return readlane64(v, l); }
+
 struct Sel {
     int d;   // delta of the selected bit
     int i;   // global bit index
@@ -131,8 +136,11 @@ struct Walker {
     const WT *__restrict__ W;
     int64_t ld;
     int n, lane;
-    uint64_t xb, bb;          // X and BEST bits of this lane (bit j)
-    uint64_t vb;              // valid-element bits of this lane (bit j set iff bit index < n)
+    // per-lane bit masks over the lane's EPL elements: one register when they fit
+    typedef typename MaskOf<(EPL <= 32)>::type mask_t;
+    static constexpr mask_t ONE = 1;
+    mask_t xb, bb;            // X and BEST bits of this lane (bit j)
+    mask_t vb;                // valid-element bits of this lane (bit j set iff bit index < n)
     int64_t E, Eb;
     int ring;                 // tabu ring (see above); -1: nothing to clear
     // Step 1 state of the current vector: per-lane least word over all bits
@@ -183,7 +191,7 @@ struct Walker {
             for (int e = 0; e < V; ++e) {
                 const int j = s * V + e;
                 const int k = gidx(s, e);
-                if (k < n) vb |= 1ull << j;
+                if (k < n) vb |= ONE << j;
                 kb.set(j, k < n ? diag[k] * (1 << KB) + j + KBIAS : KB_PAD);   // X = 0: Delta_k = W_kk
                 mul.set(j, (sizeof(WT) == 2 && (j & 1)) ? (int)((uint32_t)MUL0 << 16) : MUL0);
             }
@@ -255,7 +263,7 @@ struct Walker {
     __device__ __forceinline__ void flip_bit(const Sel &s, F &&during) {
         uint4 q[SLOTS];
         load_row(s.i, q);
-        const bool xi = (readlane64(xb, s.L) >> s.j) & 1;
+        const bool xi = (lane_mask(xb, s.L) >> s.j) & 1;
         during();
         apply_row(q, xi ? -1 : 1);
         const int o = kb[s.j];
@@ -263,7 +271,7 @@ struct Walker {
         const int mo = mul[s.j];
         const uint32_t mf = (sizeof(WT) == 2 && (s.j & 1)) ? (MFLIP << 16) : MFLIP;
         mul.set(s.j, lane == s.L ? (int)((uint32_t)mo ^ mf) : mo);
-        xb ^= lane == s.L ? (1ull << s.j) : 0ull;
+        xb ^= lane == s.L ? (ONE << s.j) : (mask_t)0;
     }
 
     __device__ __forceinline__ Sel sel_of(int i) {
@@ -363,7 +371,7 @@ struct Walker {
         if (E + d < Eb) {
             const Sel s = argmin_from(kminU, mU);
             Eb = E + d;
-            bb = xb ^ (lane == s.L ? (1ull << s.j) : 0ull);
+            bb = xb ^ (lane == s.L ? (ONE << s.j) : (mask_t)0);
             note_best();
         }
     }
@@ -494,7 +502,7 @@ struct Walker {
             const uint64_t f = ((word >> (k0 & 63)) & ((1ull << V) - 1)) & (vb >> (s * V));   // bits >= n ignored
             db |= f << (s * V);
         }
-        const uint64_t diff = xb ^ db;
+        const mask_t diff = xb ^ (mask_t)db;
         int hd = 0;
 #pragma unroll
         for (int j = 0; j < EPL; ++j) {
