@@ -398,43 +398,71 @@ __global__ void k_pool_counts(const uint64_t *__restrict__ bits, int P, int m, i
 }
 
 // Features of every pooled vector (one workgroup per entry (q, r)).  The
-// local field h_k = W_kk + 2 sum_{j != k} W_kj x_j is accumulated in LDS over
-// the set bits j of the entry (the packed W has a zero diagonal).  need
-// (nullable): only the entries flagged there are computed (the parents that
-// this round's learned operations read), and their flags are cleared.
+// local field h_k = W_kk + 2 sum_{j != k} W_kj x_j is accumulated in
+// registers (thread t holds k = t + 256 i) over the set bits j of the entry,
+// four rows at a time so that their loads are in flight together (the packed
+// W has a zero diagonal and zero padding up to its row stride, which covers
+// 256 ceil(n/256)).  need (nullable): only the entries flagged there are
+// computed (the parents that this round's learned operations read), and
+// their flags are cleared.
+constexpr int FEAT_NPT = 16;      // n <= 4096 = 256 x 16
 template <typename WT>
 __global__ __launch_bounds__(256) void k_features(const WT *__restrict__ W, const int *__restrict__ diag,
                                                   const int64_t *__restrict__ rowabs, int64_t ld, int n, int nw,
                                                   int64_t bound, const uint64_t *__restrict__ bits, int m,
                                                   const int *__restrict__ cnt, short *__restrict__ feat,
                                                   int *__restrict__ need) {
-    __shared__ int h[4096];
     __shared__ int wanted;
     const int cell = blockIdx.x, q = cell / m, r = cell % m;
+    const int tid = (int)threadIdx.x;
     if (need) {
-        if (threadIdx.x == 0) wanted = need[cell];
+        if (tid == 0) wanted = need[cell];
         __syncthreads();
         if (!wanted) return;              // the whole workgroup leaves together
-        if (threadIdx.x == 0) need[cell] = 0;
+        if (tid == 0) need[cell] = 0;
     }
     const uint64_t *x = bits + (int64_t)cell * nw;
     const uint64_t *best = bits + (int64_t)q * m * nw;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] = diag[k];
+    const int npt = (n + 255) / 256;
+    int h[FEAT_NPT];
+#pragma unroll
+    for (int i = 0; i < FEAT_NPT; ++i) h[i] = 0;
+    // rows js[0..3]; the rows past cnt_j repeat js[0] and count zero times
+    auto add_rows = [&](const int (&js)[4], int cnt_j) {
+        const WT *r0 = W + (int64_t)js[0] * ld + tid, *r1 = W + (int64_t)js[1] * ld + tid;
+        const WT *r2 = W + (int64_t)js[2] * ld + tid, *r3 = W + (int64_t)js[3] * ld + tid;
+        const int c1 = cnt_j > 1, c2 = cnt_j > 2, c3 = cnt_j > 3;
+#pragma unroll
+        for (int i = 0; i < FEAT_NPT; ++i) {
+            if (i < npt) {
+                const int o = 256 * i;
+                h[i] += 2 * ((int)r0[o] + c1 * (int)r1[o] + c2 * (int)r2[o] + c3 * (int)r3[o]);
+            }
+        }
+    };
     for (int wd = 0; wd < nw; ++wd) {
         uint64_t word = x[wd];
         if (wd == nw - 1 && (n & 63)) word &= (1ull << (n & 63)) - 1;   // bits >= n are not part of X
         while (word) {
-            const int j = wd * 64 + __builtin_ctzll(word);
-            word &= word - 1;
-            const WT *row = W + (int64_t)j * ld;
-            for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] += 2 * (int)row[k];
+            // up to four set bits of this word
+            int js[4];
+            int c = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                js[u] = word ? wd * 64 + __builtin_ctzll(word) : js[0];
+                c += word ? 1 : 0;
+                word &= word - 1;
+            }
+            add_rows(js, c);
         }
     }
-    __syncthreads();
     const float fB = (float)bound, fm = (float)m;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < FEAT_NPT; ++i) {
+        const int k = tid + 256 * i;
+        if (i >= npt || k >= n) continue;
         const int xk = (int)((x[k >> 6] >> (k & 63)) & 1), bk = (int)((best[k >> 6] >> (k & 63)) & 1);
-        const int delta = (1 - 2 * xk) * h[k];
+        const int delta = (1 - 2 * xk) * (diag[k] + h[i]);
         float f[NF];
         f[0] = (float)delta / fB;
         f[1] = (float)(2 * xk - 1);
