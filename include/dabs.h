@@ -375,7 +375,8 @@ int dabs_batched_set_cancel(dabs_batched *b, const volatile int32_t *flag_host);
  * Autotuner: for every size class of the batch (weight type x slot count),
  * times each compiled variant of the batch-search kernel on the batch's own
  * next-round items and keeps the fastest for the following rounds:
- *   0  W rows from global memory / L2, registers capped for 4 waves per SIMD,
+ *   0  W rows from global memory / L2, registers capped for 4 waves per SIMD
+ *      (2 for classes of eight slots),
  *   1  the same with the register file uncapped,
  *   2  W staged in LDS, one copy per workgroup of four waves (classes of one
  *      slot whose every W fits in 40 KB; -1 ms for other classes).
@@ -389,6 +390,12 @@ int dabs_batched_set_cancel(dabs_batched *b, const volatile int32_t *flag_host);
  */
 #define DABS_WALK_VARIANTS 3
 int dabs_batched_autotune(dabs_batched *b, double *ms_out, int32_t *choice_out, void *stream);
+/* Pins size class `cls` (an index into dabs_batched_classes) to `variant`
+ * instead of timing them; results do not depend on the variant, only speed.
+ * Variant 0 caps registers for 4 waves per SIMD (2 for classes of eight
+ * slots).  DABS_E_INVALID: bad class or variant, or variant 2 for a class
+ * whose W does not all fit in LDS.  Host only (no stream). */
+int dabs_batched_set_variant(dabs_batched *b, int32_t cls, int32_t variant);
 int dabs_solver_autotune(dabs_solver *s, double *ms_out, int32_t *choice_out, void *stream);
 int dabs_batched_classes(const dabs_batched *b, int32_t *wtype_slots_count_variant, int32_t cap);
 

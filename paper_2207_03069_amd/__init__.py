@@ -113,6 +113,7 @@ _SIGS = {
     "dabs_batched_autotune": ([_P, _P, _P, _P], C.c_int),
     "dabs_solver_autotune": ([_P, _P, _P, _P], C.c_int),
     "dabs_batched_classes": ([_P, _P, C.c_int32], C.c_int),
+    "dabs_batched_set_variant": ([_P, C.c_int32, C.c_int32], C.c_int),
     "dabs_batched_set_mlp": ([_P, _P], C.c_int),
 }
 
@@ -520,6 +521,10 @@ def dabs_batched_classes(b: Batched):
     out = (C.c_int32 * (4 * max(nc, 1)))()
     lib().dabs_batched_classes(b.handle, C.cast(out, C.c_void_p), nc)
     return [tuple(out[4 * c:4 * c + 4]) for c in range(nc)]
+
+
+def dabs_batched_set_variant(b: Batched, cls: int, variant: int):
+    _check(lib().dabs_batched_set_variant(b.handle, cls, variant))
 
 
 def walk_slots(wtype: int, n: int) -> int:

@@ -1031,6 +1031,21 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
     return status;
 }
 
+int dabs_batched_set_variant(dabs_batched *s, int32_t cls, int32_t variant) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
+    if (cls < 0 || cls >= (int)s->classes.size()) return dabs_fail(DABS_E_INVALID, "no size class %d", cls);
+    if (variant < 0 || variant >= WALK_VARIANTS) return dabs_fail(DABS_E_INVALID, "no variant %d", variant);
+    if (variant == 2 && s->classes[cls].lds_bytes <= 0)
+        return dabs_fail(DABS_E_INVALID, "class %d: W does not fit in LDS", cls);
+    if (s->classes[cls].variant != variant && s->graph_ready) {   // the captured round has the old kernel
+        (void)hipGraphExecDestroy(s->exec);
+        (void)hipGraphDestroy(s->graph);
+        s->graph_ready = false;
+    }
+    s->classes[cls].variant = variant;
+    return DABS_OK;
+}
+
 int dabs_batched_classes(const dabs_batched *s, int32_t *wtype_slots_count_variant, int32_t cap) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
     const int nc = (int)s->classes.size();

@@ -106,7 +106,11 @@ __global__ __launch_bounds__(256) void k_walk_lds(WalkArgs a) {
 // loops so that lanes 1..63 re-enter the pop without lane 0 (and read item 0
 // again, forever).
 // WPE: the minimum waves per SIMD the register allocation must allow (4 caps
-// a wave at 128 VGPRs; 1 leaves the whole register file to the allocator).
+// a wave at 128 VGPRs, 2 at 256; 1 leaves the whole register file to the
+// allocator).  The capped variant asks for 4 waves, except with eight slots,
+// whose 128 key and multiplier words alone fill 128 registers: there it asks
+// for 2.
+template <int SLOTS> constexpr int CAPPED_WPE = SLOTS >= 8 ? 2 : 4;
 template <typename WT, int SLOTS, bool LDSW>
 __device__ __forceinline__ void walk_item(const ItemsArgs &a, int2 item, lds_ptr<const WT> Wl) {
     typedef typename Walker<WT, SLOTS, LDSW>::vecH vecH;
@@ -176,7 +180,7 @@ static hipError_t go_items(int variant, const ItemsArgs &a, hipStream_t st) {
         return hipErrorInvalidValue;
     }
     if (variant == 0)
-        hipLaunchKernelGGL((k_walk_items<WT, SLOTS, 4>), dim3(a.nitems), dim3(WAVE), 0, st, a);
+        hipLaunchKernelGGL((k_walk_items<WT, SLOTS, CAPPED_WPE<SLOTS>>), dim3(a.nitems), dim3(WAVE), 0, st, a);
     else
         hipLaunchKernelGGL((k_walk_items<WT, SLOTS, 1>), dim3(a.nitems), dim3(WAVE), 0, st, a);
     return hipGetLastError();

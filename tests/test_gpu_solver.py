@@ -196,6 +196,61 @@ def test_batched_parity_uneven_sizes(use_graph, autotune):
         assert prog[k, 1] == ref["pool_e"].min()
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_batched_parity_each_variant(variant):
+    """Every compiled variant of the batch-search kernel, pinned for every
+    size class where it applies (W in LDS only for one-slot classes whose W
+    fit), evolves exactly as the oracle: one-slot int16 (LDS-eligible), two
+    slots int32, four and eight slots int16 (the eight-slot capped variant
+    asks for 2 waves per SIMD and spills registers)."""
+    sizes = [(40, np.int16), (300, np.int32), (1100, np.int16), (2100, np.int16)]
+    problems = [inputs.dense_qubo(n, -100, 100, 700 + k, dtype=wt) for k, (n, wt) in enumerate(sizes)]
+    kws = [dict(T=max(1, n // 10), Bn=n, tau=8, seed=50 + k, capacity=5, npools=2) for k, (n, _) in enumerate(sizes)]
+    instances = [5, 4, 3, 3]
+    rounds = 2
+    probs = [dabs.dabs_problem_create(torch.from_numpy(W).to(DEV)) for W in problems]
+    b = dabs.dabs_batched_create(probs, [dabs.ga_params(greedy_cap=CAP, **kw) for kw in kws], instances)
+    classes = dabs.dabs_batched_classes(b)
+    assert sorted(c[1] for c in classes if c[0] == dabs.DABS_W_I16) == [1, 4, 8]
+    pinned = 0
+    for c, (wtype, slots, _, _) in enumerate(classes):
+        if variant == 2 and slots != 1:
+            with pytest.raises(dabs.DabsError):
+                dabs.dabs_batched_set_variant(b, c, 2)
+            continue
+        dabs.dabs_batched_set_variant(b, c, variant)
+        pinned += 1
+    assert pinned >= 1
+    assert all(v == variant for (_, slots, _, v) in dabs.dabs_batched_classes(b) if variant != 2 or slots == 1)
+    dabs.dabs_batched_run(b, rounds, None, use_graph=True)
+    for q, W in enumerate(problems):
+        n = W.shape[0]
+        g = kws[q]
+        nw = (n + 63) // 64
+        bits = torch.zeros((g["npools"], g["capacity"], nw), dtype=torch.int64, device=DEV)
+        pe = torch.zeros((g["npools"], g["capacity"]), dtype=torch.int64, device=DEV)
+        x = torch.zeros((instances[q], nw), dtype=torch.int64, device=DEV)
+        ph = torch.zeros(instances[q], dtype=torch.int32, device=DEV)
+        dabs.dabs_batched_pools(b, q, bits, pe)
+        dabs.dabs_batched_state(b, q, x, None, ph)
+        torch.cuda.synchronize()
+        ref = oracle.solve(W, oracle.ga_params(greedy_cap=CAP, **kws[q]), instances[q], rounds)
+        assert np.array_equal(pe.cpu().numpy(), ref["pool_e"]), q
+        assert np.array_equal(inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), ref["pool_bits"]), q
+        assert np.array_equal(inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), ref["x"]), q
+        assert np.array_equal(ph.cpu().numpy().view(np.uint32), ref["ph"]), q
+
+
+def test_batched_set_variant_errors():
+    W = inputs.dense_qubo(600, -100, 100, 3)
+    b = dabs.dabs_batched_create([dabs.dabs_problem_create(torch.from_numpy(W).to(DEV))],
+                                 [dabs.ga_params(T=60, Bn=600, greedy_cap=CAP)], [2])
+    for cls, v in ((1, 0), (-1, 0), (0, 3), (0, -1), (0, 2)):
+        with pytest.raises(dabs.DabsError):
+            dabs.dabs_batched_set_variant(b, cls, v)
+    dabs.dabs_batched_set_variant(b, 0, 1)
+
+
 def test_batched_time_to_target_per_problem():
     """Per-problem targets: reachable ones are hit, unreachable ones are not."""
     problems = [inputs.dense_qubo(n, -100, 100, 70 + n) for n in (64, 200, 600)]
