@@ -299,6 +299,10 @@ int dabs_solver_record(const dabs_solver *s, uint64_t *bits_dev, int64_t *out_de
 #define DABS_STATS 50
 int dabs_solver_stats(const dabs_solver *s, int64_t *out_dev, void *stream);
 
+/* As dabs_batched_checkpoint / dabs_batched_restore for a single problem. */
+int dabs_solver_checkpoint(dabs_solver *s, void *blob_dev, int64_t *bytes, void *stream);
+int dabs_solver_restore(dabs_solver *s, const void *blob_dev, void *stream);
+
 /*
  * Cancellation (Section III-B: the device repeats batch searches until the
  * host requests termination).  flag_host is a 32-bit word of pinned host
@@ -370,6 +374,25 @@ int dabs_batched_stats(const dabs_batched *b, int32_t prob, int64_t *out_dev, vo
 /* As dabs_solver_set_cancel, for every problem of the batch (graph replays
  * included: the flag is read by the device). */
 int dabs_batched_set_cancel(dabs_batched *b, const volatile int32_t *flag_host);
+/*
+ * Checkpoint and resume.  dabs_batched_checkpoint writes the batch's whole
+ * search state between rounds into blob_dev, caller-owned device memory of
+ * *bytes bytes: the pools, every instance's X / E / phase counter and last
+ * packet, the round and flip counters, the records, the counters of the
+ * adaptive choice and each problem's record, restart and time-to-target
+ * fields, behind a header that names the batch's shape.  blob_dev == NULL
+ * only sets *bytes to the size needed; a smaller *bytes is DABS_E_INVALID.
+ * Ordered on `stream` (the header copy synchronises it).
+ * dabs_batched_restore loads such a blob into a batch created from problems
+ * of the same sizes and weight types with the same parameters and instance
+ * counts (DABS_E_INVALID otherwise, checked on the header: n, instances,
+ * pools, capacity, weight type and seed of every problem); later rounds then
+ * evolve exactly as they would have in the saved batch.  A time-to-target
+ * clock continues from its saved start tick, which is meaningful on the same
+ * device in the same process only.  Synchronises `stream` for the header.
+ */
+int dabs_batched_checkpoint(dabs_batched *b, void *blob_dev, int64_t *bytes, void *stream);
+int dabs_batched_restore(dabs_batched *b, const void *blob_dev, void *stream);
 
 /*
  * Autotuner: for every size class of the batch (weight type x slot count),

@@ -114,6 +114,10 @@ _SIGS = {
     "dabs_solver_autotune": ([_P, _P, _P, _P], C.c_int),
     "dabs_batched_classes": ([_P, _P, C.c_int32], C.c_int),
     "dabs_batched_set_variant": ([_P, C.c_int32, C.c_int32], C.c_int),
+    "dabs_batched_checkpoint": ([_P, _P, _P, _P], C.c_int),
+    "dabs_batched_restore": ([_P, _P, _P], C.c_int),
+    "dabs_solver_checkpoint": ([_P, _P, _P, _P], C.c_int),
+    "dabs_solver_restore": ([_P, _P, _P], C.c_int),
     "dabs_batched_set_mlp": ([_P, _P], C.c_int),
 }
 
@@ -521,6 +525,34 @@ def dabs_batched_classes(b: Batched):
     out = (C.c_int32 * (4 * max(nc, 1)))()
     lib().dabs_batched_classes(b.handle, C.cast(out, C.c_void_p), nc)
     return [tuple(out[4 * c:4 * c + 4]) for c in range(nc)]
+
+
+def _checkpoint(fn, handle, blob, stream):
+    n = C.c_int64(0)
+    if blob is None:
+        _check(fn(handle, None, C.byref(n), _stream(stream)))
+        return n.value
+    n.value = blob.numel() * blob.element_size()
+    _check(fn(handle, _ptr(blob), C.byref(n), _stream(stream)))
+    return n.value
+
+
+def dabs_batched_checkpoint(b: Batched, blob=None, stream=None) -> int:
+    """Bytes of the batch's checkpoint (blob None), or writes it into the
+    device tensor `blob` and returns its size."""
+    return _checkpoint(lib().dabs_batched_checkpoint, b.handle, blob, stream)
+
+
+def dabs_batched_restore(b: Batched, blob, stream=None):
+    _check(lib().dabs_batched_restore(b.handle, _ptr(blob), _stream(stream)))
+
+
+def dabs_solver_checkpoint(s: Solver, blob=None, stream=None) -> int:
+    return _checkpoint(lib().dabs_solver_checkpoint, s.handle, blob, stream)
+
+
+def dabs_solver_restore(s: Solver, blob, stream=None):
+    _check(lib().dabs_solver_restore(s.handle, _ptr(blob), _stream(stream)))
 
 
 def dabs_batched_set_variant(b: Batched, cls: int, variant: int):

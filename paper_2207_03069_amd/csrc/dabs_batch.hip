@@ -1031,6 +1031,115 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
     return status;
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoints: the whole search state of a batch between rounds (pools,
+// instance state, record, counters, the problems' record / restart / time-to-
+// target fields) as one device blob, restorable into a batch built from the
+// same problems, parameters and instance counts.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint64_t CKPT_MAGIC = 0x544B43534241444Eull;   // "NDABSCKT"
+constexpr uint64_t CKPT_VERSION = 1;
+struct CkptLayout {
+    std::vector<uint64_t> header;    // magic, version, shape words, then 6 words per problem
+    size_t off[17];                  // byte offsets of the segments
+    size_t bytes[17];
+    size_t total;
+};
+size_t pad8(size_t b) { return (b + 7) & ~(size_t)7; }
+CkptLayout ckpt_layout(const dabs_batched *s) {
+    CkptLayout L;
+    const int64_t rwords = s->hdesc.empty() ? 0 : s->hdesc.back().rec_word0 + s->hdesc.back().nw;
+    L.header = {CKPT_MAGIC, CKPT_VERSION, (uint64_t)s->nprob, (uint64_t)s->total_inst, (uint64_t)s->pool_cells,
+                (uint64_t)s->pool_words, (uint64_t)s->inst_words, (uint64_t)rwords};
+    for (const ProbDesc &d : s->hdesc) {
+        L.header.push_back((uint64_t)d.n);
+        L.header.push_back((uint64_t)d.instances);
+        L.header.push_back((uint64_t)d.g.npools);
+        L.header.push_back((uint64_t)d.g.capacity);
+        L.header.push_back((uint64_t)d.wtype);
+        L.header.push_back(d.g.seed);
+    }
+    const size_t inst = (size_t)s->total_inst, cells = (size_t)s->pool_cells;
+    const size_t sz[17] = {8 * L.header.size(),
+                           sizeof(ProbDesc) * (size_t)s->nprob,
+                           8 * (size_t)s->pool_words, 8 * cells, 4 * cells, 4 * cells,
+                           8 * (size_t)s->inst_words, 8 * (size_t)s->inst_words, 8 * (size_t)s->inst_words,
+                           8 * inst, 8 * inst, 4 * inst, 4 * inst, 4 * inst,
+                           8 * 4, 8 * (size_t)rwords, 8 * (size_t)STAT_WORDS * s->nprob};
+    size_t o = 0;
+    for (int k = 0; k < 17; ++k) {
+        L.off[k] = o;
+        L.bytes[k] = sz[k];
+        o += pad8(sz[k]);
+    }
+    L.total = o;
+    return L;
+}
+// device arrays in segment order (segment 0 is the header, 1 the descriptors)
+void ckpt_arrays(dabs_batched *s, void *a[17]) {
+    const BatchDev &d = s->d;
+    void *v[17] = {nullptr, d.desc, d.pool_bits, d.pool_e, d.pool_algo, d.pool_op, d.x, d.target, d.best,
+                   d.e, d.best_e, d.ph, d.algo, d.op, d.ctr, d.record, d.stats};
+    for (int k = 0; k < 17; ++k) a[k] = v[k];
+}
+}  // namespace
+
+int dabs_batched_checkpoint(dabs_batched *s, void *blob_dev, int64_t *bytes, void *stream) {
+    if (!s || !bytes) return dabs_fail(DABS_E_INVALID, "null batch or size");
+    const CkptLayout L = ckpt_layout(s);
+    if (!blob_dev) {
+        *bytes = (int64_t)L.total;
+        return DABS_OK;
+    }
+    if (*bytes < (int64_t)L.total) return dabs_fail(DABS_E_INVALID, "checkpoint needs %zu bytes", L.total);
+    hipStream_t st = (hipStream_t)stream;
+    void *a[17];
+    ckpt_arrays(s, a);
+    // the header from host memory: a synchronous copy, so the vector may go
+    HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipMemcpy(blob_dev, L.header.data(), L.bytes[0], hipMemcpyHostToDevice));
+    for (int k = 1; k < 17; ++k)
+        if (L.bytes[k])
+            HIP_OK(hipMemcpyAsync((char *)blob_dev + L.off[k], a[k], L.bytes[k], hipMemcpyDeviceToDevice, st));
+    *bytes = (int64_t)L.total;
+    return DABS_OK;
+}
+
+int dabs_batched_restore(dabs_batched *s, const void *blob_dev, void *stream) {
+    if (!s || !blob_dev) return dabs_fail(DABS_E_INVALID, "null batch or checkpoint");
+    const CkptLayout L = ckpt_layout(s);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OK(hipStreamSynchronize(st));
+    std::vector<uint64_t> h(L.header.size());
+    HIP_OK(hipMemcpy(h.data(), blob_dev, L.bytes[0], hipMemcpyDeviceToHost));
+    if (h[0] != CKPT_MAGIC || h[1] != CKPT_VERSION) return dabs_fail(DABS_E_INVALID, "not a checkpoint of this library");
+    if (h != L.header)
+        return dabs_fail(DABS_E_INVALID, "checkpoint of another batch shape (problems, instances, pools or seeds)");
+    // descriptors: the saved per-problem record, restart and time-to-target
+    // fields on this batch's own descriptors (whose pointers are this batch's)
+    std::vector<ProbDesc> saved(s->nprob);
+    HIP_OK(hipMemcpy(saved.data(), (const char *)blob_dev + L.off[1], L.bytes[1], hipMemcpyDeviceToHost));
+    std::vector<ProbDesc> cur(s->hdesc);
+    for (int p = 0; p < s->nprob; ++p) {
+        cur[p].target_e = saved[p].target_e;
+        cur[p].hit = saved[p].hit;
+        cur[p].record_e = saved[p].record_e;
+        cur[p].epoch = saved[p].epoch;
+        cur[p].record_op = saved[p].record_op;
+        cur[p].record_algo = saved[p].record_algo;
+    }
+    HIP_OK(hipMemcpy(s->d.desc, cur.data(), L.bytes[1], hipMemcpyHostToDevice));
+    void *a[17];
+    ckpt_arrays(s, a);
+    for (int k = 2; k < 17; ++k)
+        if (L.bytes[k])
+            HIP_OK(hipMemcpyAsync(a[k], (const char *)blob_dev + L.off[k], L.bytes[k], hipMemcpyDeviceToDevice, st));
+    s->armed = false;
+    for (int p = 0; p < s->nprob; ++p) s->armed = s->armed || saved[p].target_e != INT64_MIN;
+    return DABS_OK;
+}
+
 int dabs_batched_set_variant(dabs_batched *s, int32_t cls, int32_t variant) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
     if (cls < 0 || cls >= (int)s->classes.size()) return dabs_fail(DABS_E_INVALID, "no size class %d", cls);
@@ -1156,6 +1265,16 @@ int dabs_solver_record(const dabs_solver *s, uint64_t *bits_dev, int64_t *out_de
 int dabs_solver_stats(const dabs_solver *s, int64_t *out_dev, void *stream) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
     return dabs_batched_stats(s->b, 0, out_dev, stream);
+}
+
+int dabs_solver_checkpoint(dabs_solver *s, void *blob_dev, int64_t *bytes, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_checkpoint(s->b, blob_dev, bytes, stream);
+}
+
+int dabs_solver_restore(dabs_solver *s, const void *blob_dev, void *stream) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_restore(s->b, blob_dev, stream);
 }
 
 int dabs_solver_set_cancel(dabs_solver *s, const volatile int32_t *flag_host) {

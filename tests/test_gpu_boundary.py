@@ -2,9 +2,9 @@
 oracle's map (Section I, Eq. (1) -> (2)); delta bounds per size class with a
 QAP QUBO whose penalty needs more than 2^23 (Section II-B, Table III shape);
 the restart of merged pools (Section IV-B) and the run's record against the
-oracle's generational loop; and cancellation through a pinned host flag
+oracle's generational loop; cancellation through a pinned host flag
 (Section III-B: the host's termination request), with every kernel ending
-normally."""
+normally; and checkpoints restored into fresh solvers and batches."""
 import time
 
 import numpy as np
@@ -265,3 +265,100 @@ def test_cancel_flag_must_be_pinned():
     s = dabs.dabs_solver_create(p, dabs.ga_params(T=3, Bn=30), 4)
     with pytest.raises(ValueError):
         dabs.dabs_solver_set_cancel(s, torch.zeros(1, dtype=torch.int32))
+
+
+# ---------------------------------------------------------------- checkpoint
+def test_checkpoint_restore_continues_exactly():
+    """A checkpoint after 3 rounds, restored into a fresh solver, continues
+    exactly as the saved solver does and as the oracle's uninterrupted loop
+    (restarts of merged pools, the record and the choice counters included)."""
+    n, inst, P, m = 60, 32, 2, 4
+    W = inputs.dense_qubo(n, -50, 50, 13 + n)
+    kw = dict(T=6, Bn=n, tau=4, seed=6, capacity=m, npools=P, greedy_cap=100000, flags=dabs.DABS_GA_RESTART,
+              merge_hamming=14)
+    p = dabs.dabs_problem_create(dev(W))
+    a = dabs.dabs_solver_create(p, dabs.ga_params(**kw), inst)
+    dabs.dabs_solver_run(a, 3)
+    nbytes = dabs.dabs_solver_checkpoint(a)
+    assert nbytes > 0
+    blob = torch.zeros(nbytes + 8, dtype=torch.uint8, device=DEV)
+    assert dabs.dabs_solver_checkpoint(a, blob) == nbytes
+    dabs.dabs_solver_run(a, 4)
+    b = dabs.dabs_solver_create(p, dabs.ga_params(**kw), inst)
+    dabs.dabs_solver_run(b, 1)                          # state to be overwritten
+    dabs.dabs_solver_restore(b, blob)
+    dabs.dabs_solver_run(b, 4)
+    ga, gb = solver_state(a, n, inst, P, m), solver_state(b, n, inst, P, m)
+    ref = oracle.solve(W, oracle.ga_params(**kw), inst, 7)
+    for k in ("pool_e", "pool_bits", "pool_algo", "pool_op", "x", "e"):
+        assert np.array_equal(ga[k], gb[k]), k
+        assert np.array_equal(gb[k], ref[k]), k
+    for k in ("best_e", "restarts", "rounds"):
+        assert ga[k] == gb[k], k
+    assert gb["rounds"] == 7 and gb["restarts"] == ref["restarts"] and gb["best_e"] == ref["best_e"]
+    st = torch.zeros((2, dabs.DABS_STATS), dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_stats(a, st[0])
+    dabs.dabs_solver_stats(b, st[1])
+    fa = torch.zeros(2, dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_state(a, total_flips=fa[0:1])
+    dabs.dabs_solver_state(b, total_flips=fa[1:2])
+    torch.cuda.synchronize()
+    assert np.array_equal(st[0].cpu().numpy(), st[1].cpu().numpy())
+    assert np.array_equal(st[1].cpu().numpy(), ref["stats"])
+    assert int(fa[0]) == int(fa[1]) == ref["flips"]
+
+
+def test_checkpoint_restore_batched_with_graph():
+    """Two problems of both weight types, graph-replayed rounds on either side
+    of the checkpoint."""
+    Ws = [inputs.dense_qubo(90, -60, 60, 1), inputs.dense_qubo(300, -60, 60, 2, dtype=np.int32)]
+    params = [dabs.ga_params(T=9, Bn=90, seed=3, capacity=5, npools=2, greedy_cap=100000),
+              dabs.ga_params(T=30, Bn=300, seed=4, capacity=6, npools=1, greedy_cap=100000)]
+    inst = [12, 7]
+    probs = [dabs.dabs_problem_create(dev(W)) for W in Ws]
+    a = dabs.dabs_batched_create(probs, params, inst)
+    dabs.dabs_batched_run(a, 2, None, use_graph=True)
+    blob = torch.zeros(dabs.dabs_batched_checkpoint(a), dtype=torch.uint8, device=DEV)
+    dabs.dabs_batched_checkpoint(a, blob)
+    dabs.dabs_batched_run(a, 3, None, use_graph=True)
+    b = dabs.dabs_batched_create(probs, params, inst)
+    dabs.dabs_batched_run(b, 1, None, use_graph=True)   # a captured round before the restore
+    dabs.dabs_batched_restore(b, blob)
+    dabs.dabs_batched_run(b, 3, None, use_graph=True)
+    for q, W in enumerate(Ws):
+        n = W.shape[0]
+        nw = (n + 63) // 64
+        g = params[q]
+        out = []
+        for s in (a, b):
+            bits = torch.zeros((g.npools, g.capacity, nw), dtype=torch.int64, device=DEV)
+            pe = torch.zeros((g.npools, g.capacity), dtype=torch.int64, device=DEV)
+            x = torch.zeros((inst[q], nw), dtype=torch.int64, device=DEV)
+            ph = torch.zeros(inst[q], dtype=torch.int32, device=DEV)
+            dabs.dabs_batched_pools(s, q, bits, pe)
+            dabs.dabs_batched_state(s, q, x, None, ph)
+            torch.cuda.synchronize()
+            out.append((bits.cpu().numpy(), pe.cpu().numpy(), x.cpu().numpy(), ph.cpu().numpy()))
+        for u, v in zip(*out):
+            assert np.array_equal(u, v), q
+
+
+def test_checkpoint_shape_mismatch_and_size():
+    W = inputs.dense_qubo(50, -9, 9, 5)
+    p = dabs.dabs_problem_create(dev(W))
+    a = dabs.dabs_solver_create(p, dabs.ga_params(T=5, Bn=50, seed=1, capacity=4, npools=2), 8)
+    dabs.dabs_solver_run(a, 1)
+    nbytes = dabs.dabs_solver_checkpoint(a)
+    small = torch.zeros(nbytes - 8, dtype=torch.uint8, device=DEV)
+    with pytest.raises(dabs.DabsError):
+        dabs.dabs_solver_checkpoint(a, small)
+    blob = torch.zeros(nbytes, dtype=torch.uint8, device=DEV)
+    dabs.dabs_solver_checkpoint(a, blob)
+    for kw, inst in ((dict(T=5, Bn=50, seed=1, capacity=4, npools=2), 9),      # other instance count
+                     (dict(T=5, Bn=50, seed=2, capacity=4, npools=2), 8),      # other seed
+                     (dict(T=5, Bn=50, seed=1, capacity=5, npools=2), 8)):     # other capacity
+        c = dabs.dabs_solver_create(p, dabs.ga_params(**kw), inst)
+        with pytest.raises(dabs.DabsError):
+            dabs.dabs_solver_restore(c, blob)
+    with pytest.raises(dabs.DabsError):
+        dabs.dabs_solver_restore(a, torch.zeros(nbytes, dtype=torch.uint8, device=DEV))   # no header
