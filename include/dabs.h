@@ -474,9 +474,9 @@ int dabs_problem_create_ising(int32_t n, int64_t nedges, const int32_t *edges_de
 /*
  * Learned proposal.  Not in the paper: a small network that scores every bit
  * of a pooled vector and two genetic operations that use the scores; the
- * exact search of Section III stays the judge (energies are never
- * approximated) and the adaptive operation choice of Section IV-A decides how
- * often the learned operations are used.
+ * exact search of Section III still evaluates every vector (energies are
+ * never approximated) and the adaptive operation choice of Section IV-A
+ * decides how often the learned operations are used.
  *
  * Features of bit k of pooled vector X (pool q, rank r, capacity m), float32
  * expressions rounded to bfloat16 (round to nearest even):
