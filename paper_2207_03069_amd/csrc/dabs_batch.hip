@@ -308,7 +308,28 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     for (int i0 = q; i0 < d.instances; i0 += P * WAVE) {
         const int il = i0 + lane * P;
         const int64_t el = il < d.instances ? b.best_e[d.inst0 + il] : E_INF;
-        uint64_t cand = __builtin_amdgcn_ballot_w64(el < se[m - 1]);
+        // a packet identical to an entry of the same (finite) energy pooled
+        // now is rejected whatever the packets before it do: at its turn that
+        // entry is still pooled (a duplicate) or was evicted as the worst
+        // entry (then the worst is at most its energy and the strict test
+        // fails).  Each lane checks its own packet: binary search for the
+        // entries of its energy, then their words.
+        bool pass = el < se[m - 1];
+        if (pass) {
+            int lo = 0, hi = m;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (se[mid] < el) lo = mid + 1;
+                else hi = mid;
+            }
+            const uint64_t *pw = b.best + d.inst_word0 + (int64_t)il * nw;
+            for (int r = lo; r < m && se[r] == el && pass; ++r) {
+                uint64_t diff = 0;
+                for (int w = 0; w < nw; ++w) diff |= pbits[(int64_t)r * nw + w] ^ pw[w];
+                pass = diff != 0;
+            }
+        }
+        uint64_t cand = __builtin_amdgcn_ballot_w64(pass);
         // the packet's words, one per lane (nw <= 64); the next candidate's
         // are loaded while the current one is processed
         auto words_of = [&](uint64_t c) {
