@@ -276,6 +276,10 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     __shared__ int sal[POOL_MAX], sop[POOL_MAX];
     __shared__ uint64_t pk[WAVE];
     __shared__ unsigned int hist[STAT_WORDS];
+    // with the bits in LDS, entry r of the sorted pool lives in row slot[r]:
+    // an insertion moves slot numbers, not rows, and the rows are written
+    // back in sorted order at the end
+    __shared__ int slot[POOL_MAX];
     extern __shared__ uint64_t sbits[];
     if (b.ctr[3]) return;                 // cancelled round: no packets
     const int2 pq = pools[blockIdx.x];
@@ -291,7 +295,10 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
         se[r] = pe[r];
         sal[r] = pal[r];
         sop[r] = pop[r];
+        slot[r] = r;
     }
+    // the words of sorted entry r
+    auto row = [&](int r) -> uint64_t * { return pbits + (int64_t)(bits_lds ? slot[r] : r) * nw; };
     if (bits_lds)
         for (int w = lane; w < m * nw; w += WAVE) sbits[w] = gbits[w];
     if (lane < STAT_WORDS) hist[lane] = 0;
@@ -325,7 +332,8 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
             const uint64_t *pw = b.best + d.inst_word0 + (int64_t)il * nw;
             for (int r = lo; r < m && se[r] == el && pass; ++r) {
                 uint64_t diff = 0;
-                for (int w = 0; w < nw; ++w) diff |= pbits[(int64_t)r * nw + w] ^ pw[w];
+                const uint64_t *rw = row(r);
+                for (int w = 0; w < nw; ++w) diff |= rw[w] ^ pw[w];
                 pass = diff != 0;
             }
         }
@@ -358,21 +366,28 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
                 bool same = false;
                 if (r < m && (se[r] == e || se[r] == E_INF)) {
                     uint64_t diff = 0;           // every word read (independent loads), no early exit
-                    for (int w = 0; w < nw; ++w) diff |= pbits[(int64_t)r * nw + w] ^ bits[w];
+                    const uint64_t *rw = row(r);
+                    for (int w = 0; w < nw; ++w) diff |= rw[w] ^ bits[w];
                     same = diff == 0;
                 }
                 dup = __builtin_amdgcn_ballot_w64(same) != 0;
             }
             if (dup) continue;
-            // position: the number of entries with energy <= e (they are sorted)
-            int cnt = 0;
-            for (int r = lane; r < m; r += WAVE) cnt += se[r] <= e ? 1 : 0;
-            const int pos = (int)wave_sum64(cnt);
-            // rows pos .. m-2 move down one row: the words [pos nw, (m-1) nw) go
-            // nw words up, in blocks of 4 x 64 words taken from the top, every
-            // block loaded before it is stored
+            // position: the number of entries with energy <= e (they are sorted),
+            // one ballot per 64 entries
+            int pos = 0;
+            for (int r0 = 0; r0 < m; r0 += WAVE)
+                pos += (int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(r0 + lane < m && se[r0 + lane] <= e));
+            // bits in LDS: the worst entry's row takes the newcomer's words and
+            // its slot number moves to position pos with the columns (below)
+            const int freed = bits_lds ? slot[m - 1] : 0;
+            if (bits_lds)
+                for (int w = lane; w < nw; w += WAVE) sbits[(int64_t)freed * nw + w] = bits[w];
+            // bits in global memory: rows pos .. m-2 move down one row: the words
+            // [pos nw, (m-1) nw) go nw words up, in blocks of 4 x 64 words taken
+            // from the top, every block loaded before it is stored
             const int64_t lo = (int64_t)pos * nw;
-            for (int64_t top = (int64_t)(m - 1) * nw; top > lo; top -= 4 * WAVE) {
+            for (int64_t top = bits_lds ? lo : (int64_t)(m - 1) * nw; top > lo; top -= 4 * WAVE) {
                 uint64_t v[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -387,26 +402,30 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
                 }
                 __syncthreads();
             }
-            for (int w = lane; w < nw; w += WAVE) pbits[(int64_t)pos * nw + w] = bits[w];
-            // the columns likewise, 64 entries at a time from the top
+            if (!bits_lds)
+                for (int w = lane; w < nw; w += WAVE) pbits[(int64_t)pos * nw + w] = bits[w];
+            // the columns (and slot numbers) likewise, 64 entries at a time from the top
             for (int top = m - 1; top > pos; top -= WAVE) {
                 const int r = top - lane;
                 long long ve = 0;
-                int va = 0, vo = 0;
+                int va = 0, vo = 0, vs = 0;
                 if (r > pos) {
                     ve = se[r - 1];
                     va = sal[r - 1];
                     vo = sop[r - 1];
+                    vs = slot[r - 1];
                 }
                 __syncthreads();
                 if (r > pos) {
                     se[r] = ve;
                     sal[r] = va;
                     sop[r] = vo;
+                    slot[r] = vs;
                 }
                 __syncthreads();
             }
             if (lane == 0) {
+                slot[pos] = freed;
                 se[pos] = e;
                 sal[pos] = b.algo[gi];
                 sop[pos] = b.op[gi];
@@ -422,7 +441,7 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
         pop[r] = sop[r];
     }
     if (bits_lds)
-        for (int w = lane; w < m * nw; w += WAVE) gbits[w] = sbits[w];
+        for (int w = lane; w < m * nw; w += WAVE) gbits[w] = sbits[(int64_t)slot[w / nw] * nw + w % nw];
     if (lane < STAT_WORDS && hist[lane])
         atomicAdd(&b.stats[(int64_t)pq.x * STAT_WORDS + lane], (unsigned long long)hist[lane]);
 }
