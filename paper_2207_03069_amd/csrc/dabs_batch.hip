@@ -1077,6 +1077,8 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
 // target fields) as one device blob, restorable into a batch built from the
 // same problems, parameters and instance counts.
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
 namespace {
 constexpr uint64_t CKPT_MAGIC = 0x544B43534241444Eull;   // "NDABSCKT"
 constexpr uint64_t CKPT_VERSION = 1;
@@ -1124,6 +1126,8 @@ void ckpt_arrays(dabs_batched *s, void *a[17]) {
     for (int k = 0; k < 17; ++k) a[k] = v[k];
 }
 }  // namespace
+
+extern "C" {
 
 int dabs_batched_checkpoint(dabs_batched *s, void *blob_dev, int64_t *bytes, void *stream) {
     if (!s || !bytes) return dabs_fail(DABS_E_INVALID, "null batch or size");
