@@ -271,6 +271,17 @@ __global__ __launch_bounds__(256) void k_sort_items(BatchDev b, int2 *items, con
 // bits_lds: with a nonzero size of dynamic LDS (at least capacity x nwords
 // words for every pool of the batch), the pool's bits are worked on in LDS
 // as well and written back at the end.
+// Hash of a packed bit vector for the duplicate tests of the insertion: the
+// XOR over words of a 64-bit finaliser (SplitMix64's) of word + index
+// constant, so that lanes can hash words in any order.  Equal vectors have
+// equal hashes; equal hashes are confirmed word by word.
+__device__ __forceinline__ uint64_t word_mix(uint64_t v, int w) {
+    uint64_t z = v + 0x9E3779B97F4A7C15ull * (uint64_t)(w + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pools, int bits_lds) {
     __shared__ long long se[POOL_MAX];
     __shared__ int sal[POOL_MAX], sop[POOL_MAX];
@@ -280,6 +291,7 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
     // an insertion moves slot numbers, not rows, and the rows are written
     // back in sorted order at the end
     __shared__ int slot[POOL_MAX];
+    __shared__ uint64_t shash[POOL_MAX];  // word hash of sorted entry r (moves with the columns)
     extern __shared__ uint64_t sbits[];
     if (b.ctr[3]) return;                 // cancelled round: no packets
     const int2 pq = pools[blockIdx.x];
@@ -303,6 +315,13 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
         for (int w = lane; w < m * nw; w += WAVE) sbits[w] = gbits[w];
     if (lane < STAT_WORDS) hist[lane] = 0;
     __syncthreads();
+    for (int r = lane; r < m; r += WAVE) {      // one entry per lane
+        const uint64_t *rw = row(r);
+        uint64_t h = 0;
+        for (int w = 0; w < nw; ++w) h ^= word_mix(rw[w], w);
+        shash[r] = h;
+    }
+    __syncthreads();
     // the operations and algorithms the pool's instances used this round
     for (int i = q + lane * P; i < d.instances; i += P * WAVE) {
         atomicAdd(&hist[STAT_USE_OP + (b.op[d.inst0 + i] & 15)], 1u);
@@ -322,15 +341,18 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
         // fails).  Each lane checks its own packet: binary search for the
         // entries of its energy, then their words.
         bool pass = el < se[m - 1];
+        uint64_t ph = 0;                         // the lane's packet hash
         if (pass) {
+            const uint64_t *pw = b.best + d.inst_word0 + (int64_t)il * nw;
+            for (int w = 0; w < nw; ++w) ph ^= word_mix(pw[w], w);
             int lo = 0, hi = m;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (se[mid] < el) lo = mid + 1;
                 else hi = mid;
             }
-            const uint64_t *pw = b.best + d.inst_word0 + (int64_t)il * nw;
             for (int r = lo; r < m && se[r] == el && pass; ++r) {
+                if (shash[r] != ph) continue;
                 uint64_t diff = 0;
                 const uint64_t *rw = row(r);
                 for (int w = 0; w < nw; ++w) diff |= rw[w] ^ pw[w];
@@ -357,6 +379,7 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
             if (lane < nw) pk[lane] = curw;
             __syncthreads();
             const uint64_t *bits = pk;
+            const uint64_t hk = (uint64_t)readlane64(ph, t);
             // an identical vector has the same energy, unless the entry is one of
             // the initial random vectors (energy +inf, never evaluated): only
             // those entries are compared bit for bit, one entry per lane
@@ -364,7 +387,7 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
             for (int r0 = 0; r0 < m && !dup; r0 += WAVE) {
                 const int r = r0 + lane;
                 bool same = false;
-                if (r < m && (se[r] == e || se[r] == E_INF)) {
+                if (r < m && (se[r] == e || se[r] == E_INF) && shash[r] == hk) {
                     uint64_t diff = 0;           // every word read (independent loads), no early exit
                     const uint64_t *rw = row(r);
                     for (int w = 0; w < nw; ++w) diff |= rw[w] ^ bits[w];
@@ -409,11 +432,13 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
                 const int r = top - lane;
                 long long ve = 0;
                 int va = 0, vo = 0, vs = 0;
+                uint64_t vh = 0;
                 if (r > pos) {
                     ve = se[r - 1];
                     va = sal[r - 1];
                     vo = sop[r - 1];
                     vs = slot[r - 1];
+                    vh = shash[r - 1];
                 }
                 __syncthreads();
                 if (r > pos) {
@@ -421,11 +446,13 @@ __global__ __launch_bounds__(64) void k_pool_insert(BatchDev b, const int2 *pool
                     sal[r] = va;
                     sop[r] = vo;
                     slot[r] = vs;
+                    shash[r] = vh;
                 }
                 __syncthreads();
             }
             if (lane == 0) {
                 slot[pos] = freed;
+                shash[pos] = hk;
                 se[pos] = e;
                 sal[pos] = b.algo[gi];
                 sop[pos] = b.op[gi];
