@@ -70,6 +70,16 @@ def test_solver_parity(n, wt, inst, P, rounds):
     assert_same(got, ref)
 
 
+def test_solver_parity_pool_bits_in_global_memory():
+    """Pools whose bits exceed the insertion kernel's 40 KB of LDS (capacity
+    480 x 11 words) are inserted into in global memory; some rounds insert
+    many packets, later ones mostly duplicates."""
+    W = inputs.dense_qubo(700, -40, 40, 21)
+    got, ref = run_both(W, 160, 4, T=35, Bn=700, tau=8, seed=9, capacity=480, npools=1)
+    assert got["pool_e"].shape == (1, 480)
+    assert_same(got, ref)
+
+
 def test_solver_parity_two_point_one_percent():
     """The TSP workload's settings: two-point crossover, 1 % bit mutation."""
     W = inputs.dense_qubo(96, -60, 60, 3)
