@@ -259,6 +259,56 @@ def test_cancel_flag_stops_rounds_and_resume_is_exact():
     dabs.dabs_solver_destroy(ref_s)
 
 
+def test_cancel_flag_stops_graph_replayed_batch_rounds():
+    """The flag is read by the device inside replays of the captured round:
+    a batch of two problems enqueues 300 graph replays, the flag stops them,
+    and after clearing it the batch continues exactly as an uninterrupted
+    one that ran the same number of rounds."""
+    Ws = [inputs.dense_qubo(400, -80, 80, 7), inputs.dense_qubo(300, -80, 80, 8, dtype=np.int32)]
+    params = [dabs.ga_params(T=40, Bn=8 * 400, seed=5, capacity=8, npools=2, greedy_cap=100000),
+              dabs.ga_params(T=30, Bn=8 * 300, seed=6, capacity=6, npools=1, greedy_cap=100000)]
+    inst = [48, 32]
+    probs = [dabs.dabs_problem_create(dev(W)) for W in Ws]
+    b = dabs.dabs_batched_create(probs, params, inst)
+    flag = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+    dabs.dabs_batched_set_cancel(b, flag)
+    dabs.dabs_batched_run(b, 1, None, use_graph=True)
+    torch.cuda.synchronize()
+    dabs.dabs_batched_run(b, 300, None, use_graph=True)
+    time.sleep(0.05)
+    flag[0] = 1
+    torch.cuda.synchronize()
+    rec = torch.zeros(3, dtype=torch.int64, device=DEV)
+    dabs.dabs_batched_record(b, 0, None, rec)
+    torch.cuda.synchronize()
+    done = int(rec[2])
+    print("rounds completed before the flag: %d of 301" % done, flush=True)
+    assert 1 <= done < 301
+    with pytest.raises(dabs.DabsError) as e:
+        dabs.dabs_batched_run(b, 1, None, use_graph=True)
+    assert e.value.status == dabs.DABS_E_CANCELLED
+    flag[0] = 0
+    dabs.dabs_batched_run(b, 2, None, use_graph=True)
+    ref = dabs.dabs_batched_create(probs, params, inst)
+    dabs.dabs_batched_run(ref, done + 2, None, use_graph=True)
+    for q, W in enumerate(Ws):
+        n = W.shape[0]
+        nw = (n + 63) // 64
+        g = params[q]
+        out = []
+        for s in (b, ref):
+            bits = torch.zeros((g.npools, g.capacity, nw), dtype=torch.int64, device=DEV)
+            pe = torch.zeros((g.npools, g.capacity), dtype=torch.int64, device=DEV)
+            x = torch.zeros((inst[q], nw), dtype=torch.int64, device=DEV)
+            dabs.dabs_batched_pools(s, q, bits, pe)
+            dabs.dabs_batched_state(s, q, x)
+            torch.cuda.synchronize()
+            out.append((bits.cpu().numpy(), pe.cpu().numpy(), x.cpu().numpy()))
+        for u, v in zip(*out):
+            assert np.array_equal(u, v), q
+    dabs.dabs_batched_set_cancel(b, None)
+
+
 def test_cancel_flag_must_be_pinned():
     W = inputs.dense_qubo(30, -5, 5, 1)
     p = dabs.dabs_problem_create(dev(W))
