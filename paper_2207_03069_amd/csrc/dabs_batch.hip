@@ -676,7 +676,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         d.pool_bit0 = pbits;
         d.W = pr->W; d.rowptr = pr->rowptr; d.nz = pr->nz;
         d.diag = pr->diag; d.ld = pr->ld; d.n = pr->n; d.nw = (pr->n + 63) / 64;
-        d.wtype = pr->wtype; d.slots = pr->slots;
+        d.wtype = pr->wtype; d.slots = pr->slots; d.wmax2 = 2 * pr->wmax;
         d.instances = instances[p]; d.inst0 = (int32_t)inst;
         d.g = params[p];
         d.pool_cell0 = cells; d.pool_word0 = pwords; d.inst_word0 = iwords;

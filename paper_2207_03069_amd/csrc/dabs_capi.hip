@@ -36,19 +36,23 @@ constexpr long long I24_MAX = (1 << 23) - 1;
 // diagonal).  bad: bit 0 asymmetric, bit 1 an int16 -32768 off the diagonal
 // (the search negates off-diagonal int16 weights in 16 bits), bit 2 an int32
 // weight off the diagonal outside the 24-bit multiply's operand range.
+// bad[1] receives the largest |W_ij| off the diagonal (clamped to 2^31 - 1).
 template <typename WT>
 __global__ __launch_bounds__(256) void k_validate(const WT *__restrict__ W, int64_t ld, int n,
                                                   int *__restrict__ bad, long long *__restrict__ rowb) {
     const int i = blockIdx.x;
-    long long acc = 0;
+    long long acc = 0, amax = 0;
     int asym = 0;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const long long a = W[(int64_t)i * ld + j], b = W[(int64_t)j * ld + i];
         asym |= a != b;
         if (sizeof(WT) == 2 && j != i && a == -32768) asym |= 2;
         if (sizeof(WT) == 4 && j != i && (a > I24_MAX || a < -I24_MAX)) asym |= 4;
-        acc += (j == i ? 1 : 2) * (a < 0 ? -a : a);
+        const long long aa = a < 0 ? -a : a;
+        acc += (j == i ? 1 : 2) * aa;
+        if (j != i && aa > amax) amax = aa;
     }
+    if (amax > 0) atomicMax(&bad[1], (int)(amax > 0x7FFFFFFFll ? 0x7FFFFFFFll : amax));
     __shared__ long long part[256];
     __shared__ int pbad[256];
     part[threadIdx.x] = acc;
@@ -197,22 +201,23 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     long long *rowb = nullptr;
     void *Wp = nullptr;
     int *diag = nullptr;
-    if (hipMalloc(&bad, sizeof(int)) != hipSuccess || hipMalloc(&rowb, sizeof(long long) * n) != hipSuccess ||
+    if (hipMalloc(&bad, 2 * sizeof(int)) != hipSuccess || hipMalloc(&rowb, sizeof(long long) * n) != hipSuccess ||
         hipMalloc(&Wp, es * (size_t)n * (size_t)ldp) != hipSuccess || hipMalloc(&diag, sizeof(int) * n) != hipSuccess) {
         (void)hipFree(bad); (void)hipFree(rowb); (void)hipFree(Wp); (void)hipFree(diag);
         return dabs_fail(DABS_E_NOMEM, "allocating %zu bytes for W", es * (size_t)n * (size_t)ldp);
     }
     int status = DABS_OK;
     long long *hb = (long long *)malloc(sizeof(long long) * n);
-    int hbad = 0;
+    int hbad2[2] = {0, 0};
+    int &hbad = hbad2[0];
     do {
-        if (hipMemsetAsync(bad, 0, sizeof(int), st) != hipSuccess) { status = DABS_E_HIP; break; }
+        if (hipMemsetAsync(bad, 0, 2 * sizeof(int), st) != hipSuccess) { status = DABS_E_HIP; break; }
         if (wtype == DABS_W_I16)
             hipLaunchKernelGGL(k_validate<int16_t>, dim3(n), dim3(256), 0, st, (const int16_t *)w_dev, ld, n, bad, rowb);
         else
             hipLaunchKernelGGL(k_validate<int32_t>, dim3(n), dim3(256), 0, st, (const int32_t *)w_dev, ld, n, bad, rowb);
         if (hipGetLastError() != hipSuccess) { status = DABS_E_HIP; break; }
-        if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        if (hipMemcpyAsync(hbad2, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(hb, rowb, sizeof(long long) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) { status = DABS_E_HIP; break; }
     } while (0);
@@ -252,6 +257,7 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     p->wtype = wtype;
     p->ld = ldp;
     p->bound = bound;
+    p->wmax = hbad2[1];
     p->W = Wp;
     p->diag = diag;
     p->rowabs = (int64_t *)rowb;
@@ -342,7 +348,7 @@ int dabs_search(const dabs_problem *p, const dabs_search_params *sp, int32_t cou
     if (trace_dev && trace_cap < 1) return dabs_fail(DABS_E_INVALID, "trace_cap must be >= 1");
     WalkArgs a;
     memset(&a, 0, sizeof(a));
-    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
+    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count; a.wmax2 = 2 * p->wmax;
     a.batch = 0; a.rule = sp->rule; a.T = sp->T; a.tau = sp->tau; a.greedy_cap = sp->greedy_cap;
     a.seed = sp->seed; a.phase = sp->phase; a.inst0 = sp->inst0;
     a.x = x_dev; a.target = target_dev; a.best = best_dev; a.best_e = best_e_dev; a.e = e_dev;
@@ -363,7 +369,7 @@ int dabs_batch_search(const dabs_problem *p, const dabs_batch_params *bp, int32_
     if (bp->tau < 0 || bp->tau > TAU_MAX) return dabs_fail(DABS_E_INVALID, "tau must be in [0, %d]", TAU_MAX);
     WalkArgs a;
     memset(&a, 0, sizeof(a));
-    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count;
+    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count; a.wmax2 = 2 * p->wmax;
     a.batch = 1; a.T = bp->T; a.Bn = bp->Bn; a.tau = bp->tau; a.greedy_cap = bp->greedy_cap;
     a.seed = bp->seed; a.inst0 = bp->inst0;
     a.algo = algo_dev; a.phase_arr = phase_dev;

@@ -151,6 +151,20 @@ __device__ __forceinline__ void wave_minmin_max(int a, int b, int c, int &ra, in
     rc = max(max(readlane(c, 0), readlane(c, 16)), max(readlane(c, 32), readlane(c, 48)));
 }
 
+// Wave min of a and wave max of c, reduced together.
+__device__ __forceinline__ void wave_min_max(int a, int c, int &ra, int &rc) {
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0xB1, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0xB1, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x4E, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0x4E, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x141, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0x141, 0xF, 0xF, true));
+    a = min(a, __builtin_amdgcn_mov_dpp(a, 0x140, 0xF, 0xF, true));
+    c = max(c, __builtin_amdgcn_mov_dpp(c, 0x140, 0xF, 0xF, true));
+    ra = min(min(readlane(a, 0), readlane(a, 16)), min(readlane(a, 32), readlane(a, 48)));
+    rc = max(max(readlane(c, 0), readlane(c, 16)), max(readlane(c, 32), readlane(c, 48)));
+}
+
 // value of the neighbouring lane (l xor 1)
 __device__ __forceinline__ uint32_t swap_pair(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);

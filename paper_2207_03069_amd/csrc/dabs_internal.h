@@ -14,6 +14,7 @@ struct dabs_problem {
     void *W;             // device, n rows x ld, zero diagonal, zero padding
     int32_t *diag;       // device, n
     int64_t *rowabs;     // device, n: R_k = |W_kk| + 2 sum_{j != k} |W_kj|
+    int32_t wmax;        // max_{j != k} |W_kj|: a flip moves any other delta by at most 2 wmax
     int device;
     // sparse problems: off-diagonal rows, each nonzero one word (column in the
     // low 16 bits, weight in the high 16), and the walker's pieces per lane
@@ -34,6 +35,7 @@ struct WalkArgs {
     const int32_t *diag;
     int64_t ld;
     int32_t n, nwords, count;
+    int32_t wmax2;               // 2 max_{j != k} |W_kj|
     int32_t batch;               // 0: one phase of `rule`; 1: batch search
     int32_t rule, T, Bn, tau, greedy_cap;
     uint64_t seed;
@@ -92,7 +94,7 @@ struct ProbDesc {
     int64_t record_e;              // energy of the record (E_INF before the first round)
     int32_t epoch;                 // restarts of merged pools so far
     int32_t record_op, record_algo;// columns of the record's entry when it was last improved
-    int32_t pad_;
+    int32_t wmax2;                 // 2 max_{j != k} |W_kj| (dense problems)
 };
 // Per problem, the counters of the adaptive choice (Section IV-A): uses of
 // every operation and main algorithm, and the packets each put into a pool.

@@ -291,6 +291,7 @@ int dabs_problem_create_csr(const int32_t *row_ptr_dev, const int32_t *col_dev, 
     p->wtype = DABS_W_SPARSE;
     p->ld = 0;
     p->bound = bound;
+    p->wmax = (int32_t)(bound > 0x3FFFFFFF ? 0x3FFFFFFF : bound);   // unused by the sparse walker
     p->W = nullptr;
     p->diag = diag;
     p->rowabs = (int64_t *)rowb;

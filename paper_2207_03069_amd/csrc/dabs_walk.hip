@@ -39,7 +39,7 @@ __device__ __forceinline__ void walk_one(const WalkArgs &a, int wid, lds_ptr<con
     typedef typename Walker<WT, SLOTS, LDSW>::vecH vecH;
     vecH kb0, kb1, mul0, mul1;
     Walker<WT, SLOTS, LDSW> w(kb0, kb1, mul0, mul1);
-    w.setup((const WT *)a.W, a.diag, a.ld, a.n, a.seed, a.inst0 + (uint32_t)wid);
+    w.setup((const WT *)a.W, a.diag, a.ld, a.n, a.seed, a.inst0 + (uint32_t)wid, a.wmax2);
     w.Wl = Wl;
     w.ldl = lds_row<WT>(a.n);
     uint64_t *x = a.x + (int64_t)wid * a.nwords;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void walk_item(const ItemsArgs &a, int2 item, lds_ptr
     const int p = __builtin_amdgcn_readfirstlane(item.x), i = __builtin_amdgcn_readfirstlane(item.y);
     ProbDesc *d = b.desc + p;
     Walker<WT, SLOTS, LDSW> w(kb0, kb1, mul0, mul1);
-    w.setup((const WT *)d->W, d->diag, d->ld, d->n, d->g.seed, (uint32_t)i);
+    w.setup((const WT *)d->W, d->diag, d->ld, d->n, d->g.seed, (uint32_t)i, d->wmax2);
     w.Wl = Wl;
     w.ldl = lds_row<WT>(d->n);
     const int64_t gi = d->inst0 + i;

@@ -147,6 +147,16 @@ struct Walker {
     // and its wave minimum (as kb >> LOGV)
     uint32_t kminU;
     int mU;
+    // Step 1 can only change BEST when E + min_k Delta_k < E(BEST).  lbU is a
+    // lower bound of min_k Delta_k at the current vector: exact after a
+    // reduction over all bits, and after a flip of bit i with delta d at
+    // least min(lbU - 2 max|W_ik|, -d) (every other delta moves by
+    // 2 |W_ik| at most, the flipped one becomes -d).  While E + lbU >= E(BEST)
+    // the reduction over all bits is not made; exU says whether kminU / mU
+    // describe the current vector.
+    int64_t lbU;
+    bool exU;
+    int wmax2;                // 2 max_{j != k} |W_kj|
     // time to target
     int64_t target;
     unsigned long long *hit;
@@ -181,8 +191,9 @@ struct Walker {
 
     // ------------------------------------------------------------- set up
     __device__ __forceinline__ void setup(const WT *Wp, const int *diag, int64_t ld_, int n_, uint64_t seed_,
-                                          uint32_t inst_) {
-        W = Wp; ld = ld_; n = n_; seed = seed_; inst = inst_;
+                                          uint32_t inst_, int wmax2_) {
+        W = Wp; ld = ld_; n = n_; seed = seed_; inst = inst_; wmax2 = wmax2_;
+        lbU = 0; exU = false;
         lane = lane_id();
         vb = 0;
 #pragma unroll
@@ -376,17 +387,40 @@ struct Walker {
         }
     }
 
+    __device__ __forceinline__ void exact_now() {
+        lbU = dlt_w(mU);
+        exU = true;
+    }
     // Step 1 when nothing but padding is excluded.
     __device__ __forceinline__ void refresh() {
         kminU = lane_umin();
         mU = wave_min(wv(kminU));
+        exact_now();
         step1();
     }
     // Step 1 while exclusions are in force.
     __device__ __forceinline__ void refresh_all() {
         kminU = unmask(lane_umin(), lane_smin());
         mU = wave_min(wv(kminU));
+        exact_now();
         step1();
+    }
+    // Step 1 only when it can change BEST (see lbU)
+    __device__ __forceinline__ bool need1() const { return E + lbU < Eb; }
+    __device__ __forceinline__ void refresh_lazy() {
+        if (need1()) refresh();
+    }
+    __device__ __forceinline__ void refresh_all_lazy() {
+        if (need1()) refresh_all();
+    }
+    // kminU / mU of the current vector for a selection that needs them
+    // (Step 1 at this vector was made or could not change BEST)
+    __device__ __forceinline__ void ensure_exact() {
+        if (!exU) {
+            kminU = unmask(lane_umin(), lane_smin());
+            mU = wave_min(wv(kminU));
+            exact_now();
+        }
     }
     // As refresh_all(), also reducing the least word of the domain (kminM, mM)
     // in the same pass.
@@ -397,7 +431,17 @@ struct Walker {
         kminM = um;
         kminU = unmask(um, lane_smin());
         wave_min2(wv(kminU), wv(kminM), mU, mM);
+        exact_now();
         step1();
+    }
+    // the domain's least word, and Step 1 only when it can change BEST
+    __device__ __forceinline__ void refresh_dom_lazy() {
+        if (need1()) {
+            refresh_dom();
+        } else {
+            kminM = lane_umin();
+            mM = wave_min(wv(kminM));
+        }
     }
     // MaxMin's reductions: as refresh_dom's, and the domain's greatest word
     // mX (signed maximum), all from one pass over the words.
@@ -414,6 +458,19 @@ struct Walker {
         kminM = um;
         kminU = unmask(um, sm);
         wave_minmin_max(wv(kminU), wv(kminM), sx, mU, mM, mX);
+        exact_now();
+    }
+    // MaxMin's domain reductions alone (least and greatest word)
+    __device__ __forceinline__ void dom_min_max() {
+        uint32_t um = UOUT;
+        int sx = (int)0x80000000;
+#pragma unroll
+        for (int j = 0; j < EPL; j += 2) {
+            um = min(um, min((uint32_t)kb[j], (uint32_t)kb[j + 1]));
+            sx = max(sx, max(kb[j], kb[j + 1]));
+        }
+        kminM = um;
+        wave_min_max(wv(kminM), sx, mM, mX);
     }
 
     // BEST := X, then Step 1.
@@ -429,6 +486,8 @@ struct Walker {
     __device__ __forceinline__ void flip_core(const Sel &s0, F &&during) {
         const Sel s = uniform(s0);
         E += s.d;
+        lbU = min(lbU - (int64_t)wmax2, (int64_t)(-s.d));
+        exU = false;
         flip_bit(s, during);
         if (trace && flips < trace_cap && lane == 0) trace[flips] = s.i;
         flips++;
@@ -437,6 +496,10 @@ struct Walker {
     __device__ __forceinline__ void flip(const Sel &s) {
         flip_core(s);
         refresh();
+    }
+    __device__ __forceinline__ void flip_lazy(const Sel &s) {
+        flip_core(s);
+        refresh_lazy();
     }
 
     // ------------------------------------------------------------- exclusions
@@ -481,6 +544,7 @@ struct Walker {
     // Greedy (Section III-A.1): flip argmin while it is negative.
     __device__ __forceinline__ int phase_greedy(int cap) {
         if (cap <= 0) cap = 64 * n;                   // documented default bound
+        ensure_exact();
         int f = 0;
         while (dlt_w(mU) < 0 && f < cap) {
             flip(argmin_from(kminU, mU));
@@ -518,7 +582,7 @@ struct Walker {
             const Sel s = uniform(argmin_from(kminM, mM));
             mark(s);
             flip_core(s);
-            refresh_dom();
+            refresh_dom_lazy();
         }
         reset_marks();
         return f;
@@ -528,15 +592,17 @@ struct Walker {
     // The tabu mark of iteration t is set before the flip, so the refresh
     // after it reduces the domain of iteration t + 1 together with Step 1.
     __device__ __forceinline__ int phase_tabu_greedy(int T, int tau) {
+        ensure_exact();
         kminM = kminU;            // iteration 1: nothing is tabu
         mM = mU;
         for (int t = 1; t <= T; ++t) {
             const bool emp = none(mM);
+            if (emp) ensure_exact();
             const Sel s = emp ? argmin_from(kminU, mU) : argmin_from(kminM, mM);
             tabu_mark(s, t, tau, emp);
             flip_core(s);
             tabu_release(t + 1, tau);
-            refresh_dom();
+            refresh_dom_lazy();
         }
         reset_marks();
         return T;
@@ -587,7 +653,7 @@ struct Walker {
                 s = argmin_from(km, m);
             }
             flip_core(s);
-            refresh_all();
+            refresh_all_lazy();
             tabu_mark(s, t, tau, emp);
             pos = (pos + w) % n;
         }
@@ -634,7 +700,10 @@ struct Walker {
             for (int e = 0; e < V; ++e) cs[s] += (uint32_t)__builtin_popcountll(ballot(cand(s * V + e)));
             c += cs[s];
         }
-        if (c == 0) return argmin_from(kminU, mU);   // cannot happen: the domain minimum qualifies
+        if (c == 0) {                                 // cannot happen: the domain minimum qualifies
+            ensure_exact();
+            return argmin_from(kminU, mU);
+        }
         const uint32_t r = scale32(v, c);
         int slot = SLOTS - 1;
         uint32_t before = 0;
@@ -709,6 +778,7 @@ struct Walker {
         for (int t = 1; t <= T; ++t) {
             const bool ign = none(mM);      // every bit tabu: tabu ignored (R11)
             if (ign) {
+                ensure_exact();
                 mM = mU;
                 int kx = (int)0x80000000;
 #pragma unroll
@@ -724,8 +794,12 @@ struct Walker {
             tabu_mark(s, t, tau, ign);
             flip_core(s, [&] { if (t < T) prepare(t + 1); });
             tabu_release(t + 1, tau);
-            dom_minmax();
-            step1();
+            if (need1()) {
+                dom_minmax();
+                step1();
+            } else {
+                dom_min_max();
+            }
         }
         reset_marks();
         return T;
@@ -767,7 +841,7 @@ struct Walker {
             const uint32_t u = (uint32_t)readlane((int)wq, c - cbase);
             const Sel s = ign ? pick_rth<true>(dk, u) : pick_rth<false>(dk, u);
             flip_core(s);
-            refresh_all();
+            refresh_all_lazy();
             tabu_mark(s, t, tau, ign);
         }
         reset_marks();
@@ -853,6 +927,7 @@ struct Walker {
                 const uint32_t km = lane_umin();
                 const int mm = wave_min(wv(km));
                 emp = none(mm);
+                if (emp) ensure_exact();
                 s = emp ? argmin_from(kminU, mU) : argmin_from(km, mm);
             }
             flip_core(s, [&] {
@@ -863,7 +938,7 @@ struct Walker {
                     }
                 }
             });
-            refresh_all();
+            refresh_all_lazy();
             tabu_mark(s, t, tau, emp);
         }
         reset_marks();
@@ -872,10 +947,10 @@ struct Walker {
 
     // TwoNeighbor (Section III-A.7): 0, 1, 0, 2, 1, 3, 2, ...
     __device__ __forceinline__ int phase_twoneighbor() {
-        flip(sel_of(0));
+        flip_lazy(sel_of(0));
         for (int k = 1; k < n; ++k) {
-            flip(sel_of(k));
-            flip(sel_of(k - 1));
+            flip_lazy(sel_of(k));
+            flip_lazy(sel_of(k - 1));
         }
         return 2 * n - 1;
     }
