@@ -78,28 +78,36 @@ const char *dabs_last_error(void);
 /* Largest n this build supports for a weight type. */
 int32_t dabs_max_n(int32_t wtype);
 /* Largest delta bound B (see dabs_problem_create) the search accepts for n
- * bits of a weight type: 2^(29 - K) - 2 with K = max(log2 V, ceil(log2(V s)))
- * (V = 8 int16 / 4 int32 elements per 16-byte piece, s the power-of-two
- * count of 64 V-bit slots that covers n); -1 for an unsupported n or type. */
+ * bits of a weight type (Section II: every delta E(f_k X) - E(X) then fits
+ * the device's int32): 2^31 - 1 for dense W; for sparse W, its key bound
+ * (dabs_fast_bound).  -1 for an unsupported n or type. */
 int64_t dabs_max_bound(int32_t wtype, int32_t n);
+/* Largest B served by the packed-key search kernels (each delta and its bit
+ * index in one 32-bit word): 2^(29 - K) - 2 with K = max(log2 V,
+ * ceil(log2(V s))) (V = 8 int16 / 4 int32 elements per 16-byte piece, s the
+ * power-of-two count of 64 V-bit slots that covers n).  Dense problems above
+ * it, up to dabs_max_bound, run the wide-delta kernels (the same results, at
+ * a lower flip rate).  -1 for an unsupported n or type. */
+int64_t dabs_fast_bound(int32_t wtype, int32_t n);
 
 /*
  * Load a QUBO matrix (the W of Section II, Eq. (2)).
  *   w_dev  device pointer to an n x n row-major matrix of int16 (wtype
  *          DABS_W_I16) or int32 (DABS_W_I32) with row stride ld >= n elements.
  * The library validates W on the device (symmetry; delta bound
- * B = max_k |W_kk| + 2 sum_{j!=k} |W_kj| <= dabs_max_bound(wtype, n), which
- * keeps every delta and local field exact in the device representation:
- * 2^23 - 2 at n = 4096 int16, up to 2^27 - 2 at n <= 256 int32; int16
- * weights off the diagonal in [-32767, 32767], since the search negates them
- * in 16 bits; int32 weights off the diagonal in [-(2^23 - 1), 2^23 - 1], the
- * operand range of the 24-bit multiply of the update), then copies it into
- * its own padded layout.  This call synchronises `stream` once (validation
+ * B = max_k |W_kk| + 2 sum_{j!=k} |W_kj| <= dabs_max_bound(wtype, n) =
+ * 2^31 - 1, which keeps every delta and local field exact in int32), then
+ * copies it into its own padded layout and picks the search kernels: the
+ * packed-key kernels when B <= dabs_fast_bound(wtype, n) (2^23 - 2 at
+ * n = 4096 int16, up to 2^27 - 2 at n <= 256 int32), int16 weights off the
+ * diagonal lie in [-32767, 32767] (that update negates them in 16 bits) and
+ * int32 weights off the diagonal in [-(2^23 - 1), 2^23 - 1] (the operand
+ * range of its 24-bit multiply); the wide-delta kernels otherwise
+ * (dabs_problem_wide).  This call synchronises `stream` once (validation
  * result); the caller may free w_dev afterwards.
  * Errors: DABS_E_INVALID (null, n < 1, ld < n, bad wtype), DABS_E_UNSUPPORTED
  * (n > dabs_max_n), DABS_E_NOT_SYMMETRIC, DABS_E_RANGE (B above
- * dabs_max_bound, or an off-diagonal weight outside the ranges above),
- * DABS_E_NOMEM, DABS_E_HIP.  *out is set only on success.
+ * dabs_max_bound), DABS_E_NOMEM, DABS_E_HIP.  *out is set only on success.
  */
 int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
                         void *stream, dabs_problem **out);
@@ -127,6 +135,18 @@ int dabs_problem_create_csr(const int32_t *row_ptr_dev, const int32_t *col_dev, 
 int dabs_problem_destroy(dabs_problem *p);
 /* n, weight type and delta bound B of a loaded problem (any pointer may be NULL). */
 int dabs_problem_info(const dabs_problem *p, int32_t *n, int32_t *wtype, int64_t *bound);
+/* 1 when the problem's searches run the wide-delta kernels (deltas as plain
+ * int32 words, domains as bit masks), 0 for the packed-key kernels; a
+ * negative status for a NULL problem. */
+int32_t dabs_problem_wide(const dabs_problem *p);
+/* Choose the kernels of a dense problem: 1 the wide-delta kernels (any dense
+ * W), 0 the packed-key kernels (only W that dabs_problem_create would give
+ * them).  Both give identical results.  Read when a search call is made and
+ * when a solver or batch is created (existing ones keep their choice).
+ * Errors: DABS_E_INVALID (NULL, wide not 0 / 1), DABS_E_UNSUPPORTED (a
+ * sparse problem), DABS_E_RANGE (0 for W outside the packed kernels'
+ * ranges). */
+int dabs_problem_set_wide(dabs_problem *p, int32_t wide);
 
 /*
  * Energies of `count` vectors (Eq. (2)) computed from scratch.

@@ -63,6 +63,9 @@ _SIGS = {
     "dabs_last_error": ([], C.c_char_p),
     "dabs_max_n": ([C.c_int32], C.c_int32),
     "dabs_max_bound": ([C.c_int32, C.c_int32], C.c_int64),
+    "dabs_fast_bound": ([C.c_int32, C.c_int32], C.c_int64),
+    "dabs_problem_wide": ([_P], C.c_int32),
+    "dabs_problem_set_wide": ([_P, C.c_int32], C.c_int),
     "dabs_bandwidth_probe": ([C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "dabs_ising_to_qubo": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "dabs_solver_record": ([_P, _P, _P, _P], C.c_int),
@@ -189,6 +192,10 @@ def dabs_max_bound(wtype: int, n: int) -> int:
     return int(lib().dabs_max_bound(wtype, n))
 
 
+def dabs_fast_bound(wtype: int, n: int) -> int:
+    return int(lib().dabs_fast_bound(wtype, n))
+
+
 def _host_ptr(t):
     if t is None:
         return None
@@ -268,6 +275,17 @@ def dabs_problem_info(p: Problem):
     n, wt, b = C.c_int32(), C.c_int32(), C.c_int64()
     _check(lib().dabs_problem_info(p.handle, C.byref(n), C.byref(wt), C.byref(b)))
     return n.value, wt.value, b.value
+
+
+def dabs_problem_wide(p: Problem) -> int:
+    r = int(lib().dabs_problem_wide(p.handle))
+    if r < 0:
+        _check(r)
+    return r
+
+
+def dabs_problem_set_wide(p: Problem, wide: int):
+    _check(lib().dabs_problem_set_wide(p.handle, int(wide)))
 
 
 def dabs_energy(p: Problem, x, e, stream=None):

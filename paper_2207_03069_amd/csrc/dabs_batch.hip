@@ -676,7 +676,8 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         d.pool_bit0 = pbits;
         d.W = pr->W; d.rowptr = pr->rowptr; d.nz = pr->nz;
         d.diag = pr->diag; d.ld = pr->ld; d.n = pr->n; d.nw = (pr->n + 63) / 64;
-        d.wtype = pr->wtype; d.slots = pr->slots; d.wmax2 = 2 * pr->wmax;
+        d.wtype = pr->wtype; d.slots = pr->wide ? (pr->slots | WIDE_SLOTS) : pr->slots;
+        d.wmax2 = pr->wide ? 0 : 2 * pr->wmax;
         d.instances = instances[p]; d.inst0 = (int32_t)inst;
         d.g = params[p];
         d.pool_cell0 = cells; d.pool_word0 = pwords; d.inst_word0 = iwords;
@@ -712,7 +713,7 @@ static int batched_create(const dabs_problem *const *probs, int nprob, const dab
         // problem padded with dummies of instance -1)
         int lb = 0;
         for (int p : ps) {
-            const int b = lds_w_bytes(s->hdesc[p].wtype, s->hdesc[p].n);
+            const int b = (s->hdesc[p].slots & WIDE_SLOTS) ? 0 : lds_w_bytes(s->hdesc[p].wtype, s->hdesc[p].n);
             lb = (b == 0 || lb < 0) ? -1 : std::max(lb, b);
         }
         lb = lb < 0 ? 0 : lb;

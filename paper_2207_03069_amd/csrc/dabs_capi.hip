@@ -173,11 +173,17 @@ const char *dabs_last_error(void) { return g_err; }
 
 int32_t dabs_max_n(int32_t wtype) { return dabs::max_n(wtype); }
 
-int64_t dabs_max_bound(int32_t wtype, int32_t n) {
+int64_t dabs_fast_bound(int32_t wtype, int32_t n) {
     if ((wtype != DABS_W_I16 && wtype != DABS_W_I32 && wtype != DABS_W_SPARSE) || n < 1 || n > dabs::max_n(wtype))
         return -1;
     const int slots = wtype == DABS_W_SPARSE ? sparse_slots(n) : walk_slots(wtype, n);
     return ((int64_t)1 << (29 - key_shift(wtype, slots))) - 2;
+}
+
+int64_t dabs_max_bound(int32_t wtype, int32_t n) {
+    const int64_t fast = dabs_fast_bound(wtype, n);
+    if (fast < 0 || wtype == DABS_W_SPARSE) return fast;
+    return 0x7FFFFFFFll;                  // dense: every delta an int32 (the wide-delta kernels)
 }
 
 int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype, void *stream,
@@ -225,13 +231,13 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     for (int i = 0; i < n && status == DABS_OK; ++i) bound = hb[i] > bound ? hb[i] : bound;
     free(hb);
     if (status == DABS_OK && (hbad & 1)) status = dabs_fail(DABS_E_NOT_SYMMETRIC, "W is not symmetric");
-    if (status == DABS_OK && (hbad & 2))
-        status = dabs_fail(DABS_E_RANGE, "int16 W holds -32768 off the diagonal (pass it as int32)");
-    if (status == DABS_OK && (hbad & 4))
-        status = dabs_fail(DABS_E_RANGE, "int32 W holds an off-diagonal weight outside [-(2^23-1), 2^23-1]");
     const long long maxb = dabs_max_bound(wtype, n);
     if (status == DABS_OK && bound > maxb)
         status = dabs_fail(DABS_E_RANGE, "delta bound %lld above %lld for n = %d", bound, maxb, n);
+    // the packed-key kernels need B within their key words and weights their
+    // update can negate (int16) or multiply (int32, 24 bits); the wide-delta
+    // kernels take every other W
+    const bool packed_ok = bound <= dabs_fast_bound(wtype, n) && !(hbad & 6);
     if (status == DABS_OK) {
         const int gx = (int)((ldp + 255) / 256);
         if (wtype == DABS_W_I16)
@@ -266,7 +272,26 @@ int dabs_problem_create(const void *w_dev, int32_t n, int64_t ld, int32_t wtype,
     p->nz = nullptr;
     p->nnz = 0;
     p->slots = walk_slots(wtype, n);
+    p->packed_ok = packed_ok ? 1 : 0;
+    p->wide = packed_ok ? 0 : 1;
     *out = p;
+    return DABS_OK;
+}
+
+int32_t dabs_problem_wide(const dabs_problem *p) {
+    if (!p) return dabs_fail(DABS_E_INVALID, "null problem");
+    return p->wide;
+}
+
+int dabs_problem_set_wide(dabs_problem *p, int32_t wide) {
+    if (!p) return dabs_fail(DABS_E_INVALID, "null problem");
+    if (wide != 0 && wide != 1) return dabs_fail(DABS_E_INVALID, "wide must be 0 or 1");
+    if (p->wtype == DABS_W_SPARSE) return dabs_fail(DABS_E_UNSUPPORTED, "a sparse problem has no wide-delta form");
+    if (!wide && !p->packed_ok)
+        return dabs_fail(DABS_E_RANGE, "W does not fit the packed key words (delta bound %lld above %lld, or weights "
+                         "out of the packed update's range)", (long long)p->bound,
+                         (long long)dabs_fast_bound(p->wtype, p->n));
+    p->wide = wide;
     return DABS_OK;
 }
 
@@ -348,7 +373,7 @@ int dabs_search(const dabs_problem *p, const dabs_search_params *sp, int32_t cou
     if (trace_dev && trace_cap < 1) return dabs_fail(DABS_E_INVALID, "trace_cap must be >= 1");
     WalkArgs a;
     memset(&a, 0, sizeof(a));
-    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count; a.wmax2 = 2 * p->wmax;
+    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count; a.wmax2 = p->wide ? 0 : 2 * p->wmax;
     a.batch = 0; a.rule = sp->rule; a.T = sp->T; a.tau = sp->tau; a.greedy_cap = sp->greedy_cap;
     a.seed = sp->seed; a.phase = sp->phase; a.inst0 = sp->inst0;
     a.x = x_dev; a.target = target_dev; a.best = best_dev; a.best_e = best_e_dev; a.e = e_dev;
@@ -369,7 +394,7 @@ int dabs_batch_search(const dabs_problem *p, const dabs_batch_params *bp, int32_
     if (bp->tau < 0 || bp->tau > TAU_MAX) return dabs_fail(DABS_E_INVALID, "tau must be in [0, %d]", TAU_MAX);
     WalkArgs a;
     memset(&a, 0, sizeof(a));
-    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count; a.wmax2 = 2 * p->wmax;
+    a.W = p->W; a.rowptr = p->rowptr; a.nz = p->nz; a.slots = p->slots; a.diag = p->diag; a.ld = p->ld; a.n = p->n; a.nwords = (p->n + 63) / 64; a.count = count; a.wmax2 = p->wide ? 0 : 2 * p->wmax;
     a.batch = 1; a.T = bp->T; a.Bn = bp->Bn; a.tau = bp->tau; a.greedy_cap = bp->greedy_cap;
     a.seed = bp->seed; a.inst0 = bp->inst0;
     a.algo = algo_dev; a.phase_arr = phase_dev;

@@ -15,6 +15,8 @@ struct dabs_problem {
     int32_t *diag;       // device, n
     int64_t *rowabs;     // device, n: R_k = |W_kk| + 2 sum_{j != k} |W_kj|
     int32_t wmax;        // max_{j != k} |W_kj|: a flip moves any other delta by at most 2 wmax
+    int32_t wide;        // dense W searched by the wide-delta kernels (dabs_wide.h)
+    int32_t packed_ok;   // dense W that the packed-key kernels can serve (B, weight ranges)
     int device;
     // sparse problems: off-diagonal rows, each nonzero one word (column in the
     // low 16 bits, weight in the high 16), and the walker's pieces per lane
@@ -143,6 +145,12 @@ inline int lds_w_bytes(int wtype, int n) {
     return b <= LDS_W_MAX ? (int)b : 0;
 }
 hipError_t launch_walk_items(int wtype, int slots, int variant, const ItemsArgs &a, hipStream_t stream);
+// A size class of the rounds served by the wide-delta kernels carries this
+// flag in its slot count (one class per weight type and slot count).
+constexpr int WIDE_SLOTS = 0x100;
+// The wide-delta kernels (dabs_wide.hip) for a weight type and slot count.
+hipError_t launch_walk_wide(int wtype, int slots, const WalkArgs &a, hipStream_t stream);
+hipError_t launch_walk_items_wide(int wtype, int slots, const ItemsArgs &a, hipStream_t stream);
 // The sparse walker's item kernel (dabs_sparse.hip), one launch per piece count.
 hipError_t launch_sparse_items(int slots, const ItemsArgs &a, hipStream_t stream);
 // The sparse walker for dabs_search / dabs_batch_search.

@@ -197,6 +197,10 @@ int walk_slots(int wtype, int n) {
 hipError_t launch_walk_items(int wtype, int slots, int variant, const ItemsArgs &a, hipStream_t st) {
     if (variant < 0 || variant >= WALK_VARIANTS) return hipErrorInvalidValue;
     if (wtype == DABS_W_SPARSE) return launch_sparse_items(slots, a, st);
+    if (slots & WIDE_SLOTS) {                 // one kernel: variants 0 and 1 run it, no LDS form
+        if (variant == 2) return hipErrorInvalidValue;
+        return launch_walk_items_wide(wtype, slots & ~WIDE_SLOTS, a, st);
+    }
     if (wtype == DABS_W_I16) {
         switch (slots) {
         case 1: return go_items<int16_t, 1>(variant, a, st);
@@ -234,6 +238,7 @@ int max_n(int wtype) {
 hipError_t launch_walk(const dabs_problem *p, const WalkArgs &a, hipStream_t st) {
     if (p->wtype == DABS_W_SPARSE) return launch_sparse_walk(p, a, st);
     const int slots = walk_slots(p->wtype, p->n);
+    if (p->wide) return launch_walk_wide(p->wtype, slots, a, st);
     if (p->wtype == DABS_W_I16) {
         switch (slots) {
         case 1: return go<int16_t, 1>(a, st);

@@ -28,6 +28,32 @@ def dense_qubo(n: int, lo: int, hi: int, seed: int, dtype=np.int16) -> np.ndarra
     return W.astype(dtype)
 
 
+def wide_qubo(n: int, bound: int, seed: int, dtype=np.int32) -> np.ndarray:
+    """Symmetric int32 W whose delta bound max_k(|W_kk| + 2 sum_{j!=k} |W_kj|)
+    is at most `bound` and close to it: off-diagonal entries uniform in
+    [-a, a] with a = bound // (4 max(n - 1, 1)), the diagonal uniform in
+    [-bound // 2, bound // 2] (one n x n draw, upper part kept, mirrored)."""
+    rng = np.random.default_rng(seed)
+    a = bound // (4 * max(n - 1, 1))
+    U = rng.integers(-a, a + 1, size=(n, n), dtype=np.int64)
+    W = np.triu(U, 1)
+    W = W + W.T
+    np.fill_diagonal(W, rng.integers(-(bound // 2), bound // 2 + 1, size=n, dtype=np.int64))
+    return W.astype(dtype)
+
+
+def extreme_qubo(n: int, seed: int) -> np.ndarray:
+    """int32 W (n >= 3) with delta bound exactly 2^31 - 1, whose deltas reach
+    +-(2^31 - 1): W_00 = 2^30 - 1, W_11 = -(2^30 - 1), W_01 = 2^29 (rows 0
+    and 1 otherwise zero, so Delta_0 = +-(2^31 - 1) when x_1 = 1), the other
+    rows a wide_qubo block of bound 2^31 - 1."""
+    W = np.zeros((n, n), np.int64)
+    W[0, 0], W[1, 1] = (1 << 30) - 1, -((1 << 30) - 1)
+    W[0, 1] = W[1, 0] = 1 << 29
+    W[2:, 2:] = wide_qubo(n - 2, (1 << 31) - 1, seed).astype(np.int64)
+    return W.astype(np.int32)
+
+
 def maxcut_graph(n: int, p: float, seed: int):
     """Erdos-Renyi G(n, p) with +-1 edge weights of equal probability.
     Draw order: an n x n uniform matrix (edge i<j present iff U_ij < p), then

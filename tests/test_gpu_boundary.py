@@ -71,7 +71,8 @@ def test_ising_to_qubo_matches_oracle(n, m, r, seed):
                                   (np.int16, 4096), (np.int16, 2048)])
 def test_delta_bound_edges(wt, n):
     wtype = dabs.DABS_W_I16 if wt == np.int16 else dabs.DABS_W_I32
-    mb = dabs.dabs_max_bound(wtype, n)
+    mb = dabs.dabs_fast_bound(wtype, n)
+    assert dabs.dabs_max_bound(wtype, n) == (1 << 31) - 1
     # key shift: log2 of the elements a lane holds (V per 16-byte piece times
     # the power-of-two slot count), at least log2 V
     V = 8 if wt == np.int16 else 4
@@ -80,7 +81,9 @@ def test_delta_bound_edges(wt, n):
         slots *= 2
     K = max(int(np.log2(V)), int(np.ceil(np.log2(V * slots))))
     assert mb == (1 << (29 - K)) - 2
-    for B, ok in ((mb, True), (mb + 1, False)):
+    # at the packed kernels' bound they serve the problem; one above it the
+    # wide-delta kernels do
+    for B, wide in ((mb, 0), (mb + 1, 1)):
         W = np.zeros((n, n), np.int64)
         if wt == np.int32:
             W[0, 0] = B
@@ -90,25 +93,29 @@ def test_delta_bound_edges(wt, n):
             assert k + 1 <= n - 1
             W[0, 1:k + 1] = W[1:k + 1, 0] = 32767
             W[0, 0] = rem
-        p = None
-        try:
-            p = dabs.dabs_problem_create(dev(W.astype(wt)))
-            assert ok, "bound %d accepted above %d" % (B, mb)
-            assert dabs.dabs_problem_info(p)[2] == B
-        except dabs.DabsError as e:
-            assert not ok and e.status == dabs.DABS_E_RANGE
-        if p is not None:
-            dabs.dabs_problem_destroy(p)
+        p = dabs.dabs_problem_create(dev(W.astype(wt)))
+        assert dabs.dabs_problem_info(p)[2] == B
+        assert dabs.dabs_problem_wide(p) == wide
+        if wide:
+            with pytest.raises(dabs.DabsError) as e:
+                dabs.dabs_problem_set_wide(p, 0)
+            assert e.value.status == dabs.DABS_E_RANGE
+        dabs.dabs_problem_destroy(p)
 
 
 def test_int32_offdiagonal_range():
-    W = np.zeros((10, 10), np.int32)
-    W[1, 2] = W[2, 1] = (1 << 23) - 1
-    p = dabs.dabs_problem_create(dev(W))
-    dabs.dabs_problem_destroy(p)
-    W[1, 2] = W[2, 1] = 1 << 23
+    """Off-diagonal int32 weights within the packed update's 24-bit operands
+    load for the packed kernels, larger ones for the wide-delta kernels, and
+    a delta bound of 2^31 is refused."""
+    W = np.zeros((10, 10), np.int64)
+    for w, wide in (((1 << 23) - 1, 0), (1 << 23, 1), ((1 << 30) - 1, 1)):
+        W[1, 2] = W[2, 1] = w
+        p = dabs.dabs_problem_create(dev(W.astype(np.int32)))
+        assert dabs.dabs_problem_wide(p) == wide
+        dabs.dabs_problem_destroy(p)
+    W[1, 1] = 2                          # row 1: 2 + 2 (2^30 - 1) = 2^31
     with pytest.raises(dabs.DabsError) as e:
-        dabs.dabs_problem_create(dev(W))
+        dabs.dabs_problem_create(dev(W.astype(np.int32)))
     assert e.value.status == dabs.DABS_E_RANGE
 
 
@@ -126,8 +133,9 @@ def test_search_parity_near_the_bound(rule):
     W = W + W.T
     np.fill_diagonal(W, rng.integers(-(1 << 22), 1 << 22, size=n))
     B = oracle.delta_bound(W)
-    assert (1 << 23) < B <= dabs.dabs_max_bound(dabs.DABS_W_I32, n)
+    assert (1 << 23) < B <= dabs.dabs_fast_bound(dabs.DABS_W_I32, n)
     p = dabs.dabs_problem_create(dev(W.astype(np.int32)))
+    assert dabs.dabs_problem_wide(p) == 0
     X0 = inputs.random_bits(8, n, 3)
     x = dev(inputs.pack_bits(X0).view(np.int64))
     best = torch.zeros_like(x)

@@ -212,20 +212,22 @@ def test_problem_errors():
     with pytest.raises(dabs.DabsError) as ei:
         load(W)
     assert ei.value.status == dabs.DABS_E_NOT_SYMMETRIC
-    big = np.full((64, 64), 2000000, np.int32)     # B = 127 * 2e6 > 2^27 - 2, the bound at n = 64 int32
+    # B = 127 * 2e6 > 2^27 - 2, the packed bound at n = 64 int32: the wide-delta kernels
+    big = np.full((64, 64), 2000000, np.int32)
+    assert dabs.dabs_problem_wide(load(big)) == 1
+    huge = np.full((64, 64), 20000000, np.int32)   # B = 127 * 2e7 > 2^31 - 1
     with pytest.raises(dabs.DabsError) as ei:
-        load(big)
+        load(huge)
     assert ei.value.status == dabs.DABS_E_RANGE
-    # int16 weights are negated in 16 bits by the search: -32768 off the
-    # diagonal is refused, on the diagonal (kept in 32 bits) accepted
+    # the packed kernels negate int16 weights in 16 bits: -32768 off the
+    # diagonal goes to the wide-delta kernels, on the diagonal (kept in 32
+    # bits) it stays with the packed ones
     m16 = np.zeros((8, 8), np.int16)
     m16[2, 5] = m16[5, 2] = -32768
-    with pytest.raises(dabs.DabsError) as ei:
-        load(m16)
-    assert ei.value.status == dabs.DABS_E_RANGE
+    assert dabs.dabs_problem_wide(load(m16)) == 1
     d16 = np.zeros((8, 8), np.int16)
     d16[3, 3] = -32768
-    load(d16)
+    assert dabs.dabs_problem_wide(load(d16)) == 0
     too = np.zeros((dabs.dabs_max_n(dabs.DABS_W_I16) + 1,) * 2, np.int16)
     with pytest.raises(dabs.DabsError) as ei:
         load(too)

@@ -1,0 +1,320 @@
+"""GPU parity of the wide-delta search kernels (dense W whose delta bound
+does not fit the packed key words, up to B = 2^31 - 1; int16 weights of
+-32768; int32 weights beyond 24 bits) against the CPU oracle, bit for bit:
+every rule, the batch search, generational rounds on one problem and a
+graph-replayed batch that mixes packed and wide problems.  Problems within
+the packed bound are also forced onto the wide kernels (dabs_problem_set_wide)
+and must give the packed kernels' results.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_03069_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2207_03069_amd as dabs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+CAP = 100000
+B31 = (1 << 31) - 1
+RULES = [oracle.GREEDY, oracle.STRAIGHT, oracle.MAXMIN, oracle.CYCLICMIN, oracle.RANDOMMIN,
+         oracle.POSITIVEMIN, oracle.TWONEIGHBOR, oracle.TABU_GREEDY]
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def load(W, wide=None):
+    p = dabs.dabs_problem_create(to_dev(W))
+    if wide is not None:
+        dabs.dabs_problem_set_wide(p, wide)
+    return p
+
+
+def gpu_search(p, rule, X0, *, T, tau, seed, phase, inst0, targets, trace_cap):
+    cnt, n = X0.shape
+    x = to_dev(inputs.pack_bits(X0))
+    tg = to_dev(inputs.pack_bits(targets)) if targets is not None else None
+    best = torch.zeros_like(x)
+    be = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    e = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    delta = torch.zeros((cnt, n), dtype=torch.int32, device=DEV)
+    trace = torch.zeros((cnt, trace_cap), dtype=torch.int32, device=DEV)
+    flips = torch.zeros(cnt, dtype=torch.int32, device=DEV)
+    sp = dabs.dabs_search_params(rule=rule, T=T, tau=tau, greedy_cap=CAP, seed=seed, phase=phase, inst0=inst0)
+    dabs.dabs_search(p, sp, x, tg, best, be, e, delta, trace, flips)
+    torch.cuda.synchronize()
+    return dict(x=inputs.unpack_bits(x.cpu().numpy(), n), best=inputs.unpack_bits(best.cpu().numpy(), n),
+                ebest=be.cpu().numpy(), e=e.cpu().numpy(), delta=delta.cpu().numpy(), flips=flips.cpu().numpy(),
+                trace=trace.cpu().numpy())
+
+
+def check_search(W, p, rule, X0, *, T, tau, seed=31337, phase=2, inst0=4, targets=None, trace_cap=None):
+    n = W.shape[0]
+    trace_cap = trace_cap or 4 * n + 64
+    kw = dict(T=T, tau=tau, seed=seed, phase=phase, inst0=inst0, targets=targets, trace_cap=trace_cap)
+    g = gpu_search(p, rule, X0, **kw)
+    for c in range(X0.shape[0]):
+        r = oracle.search(W, rule, X0[c], T=T, tau=tau, seed=seed, inst=inst0 + c, ph=phase,
+                          target=None if targets is None else targets[c], greedy_cap=CAP, trace_cap=trace_cap)
+        ctx = "rule %d instance %d" % (rule, c)
+        assert g["flips"][c] == r["flips"], ctx
+        f = min(r["flips"], trace_cap)
+        assert np.array_equal(g["trace"][c, :f], r["trace"][:f]), ctx
+        assert np.all(g["trace"][c, f:] == -1), ctx
+        assert g["e"][c] == r["e"] and g["ebest"][c] == r["ebest"], ctx
+        assert np.array_equal(g["x"][c], r["x"]) and np.array_equal(g["best"][c], r["best"]), ctx
+        assert np.array_equal(g["delta"][c].astype(np.int64), r["delta"]), ctx
+    return g
+
+
+def full16(n, seed):
+    """int16 W over the full range, with -32768 off the diagonal."""
+    W = inputs.dense_qubo(n, -32768, 32767, seed)
+    W[0, 1] = W[1, 0] = -32768
+    return W
+
+
+def case_w(name):
+    if name == "i32-37":
+        return inputs.wide_qubo(37, B31, 37), None
+    if name == "i32-200":
+        return inputs.wide_qubo(200, B31, 200), None
+    if name == "i32-700":
+        return inputs.wide_qubo(700, B31, 700), None
+    if name == "extreme-70":
+        return inputs.extreme_qubo(70, 70), None
+    if name == "i16-300-full-range":        # -32768 off the diagonal, B above 2^23
+        return full16(300, 300), None
+    if name == "i16-513-forced":            # within the packed bound, run on the wide kernels
+        return inputs.dense_qubo(513, -300, 300, 513), 1
+    raise KeyError(name)
+
+
+CASES = ["i32-37", "i32-200", "i32-700", "extreme-70", "i16-300-full-range", "i16-513-forced"]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_wide_problem_load(case):
+    W, force = case_w(case)
+    n = W.shape[0]
+    wt = dabs.DABS_W_I16 if W.dtype == np.int16 else dabs.DABS_W_I32
+    B = oracle.delta_bound(W)
+    assert B <= dabs.dabs_max_bound(wt, n) == B31
+    p = load(W, force)
+    assert dabs.dabs_problem_wide(p) == 1
+    assert dabs.dabs_problem_info(p) == (n, wt, B)
+    if force is None:
+        off = W[~np.eye(n, dtype=bool)]
+        assert B > dabs.dabs_fast_bound(wt, n) or (W.dtype == np.int16 and (off == -32768).any())
+        with pytest.raises(dabs.DabsError) as e:
+            dabs.dabs_problem_set_wide(p, 0)
+        assert e.value.status == dabs.DABS_E_RANGE
+    X = inputs.random_bits(9, n, 5)
+    e = torch.zeros(9, dtype=torch.int64, device=DEV)
+    dabs.dabs_energy(p, to_dev(inputs.pack_bits(X)), e)
+    for c in range(9):
+        assert int(e[c]) == oracle.energy(W, X[c])
+    dabs.dabs_problem_destroy(p)
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("case", CASES)
+def test_wide_search_parity(rule, case):
+    W, force = case_w(case)
+    n = W.shape[0]
+    p = load(W, force)
+    X0 = inputs.random_bits(5, n, 3 * n)
+    X0[0, :2] = 1                       # extreme-70: Delta_0 = -(2^31 - 1) at the start
+    tg = inputs.random_bits(5, n, 4 * n)
+    tau = 0 if rule == oracle.TWONEIGHBOR else 8
+    check_search(W, p, rule, X0, T=150, tau=tau, targets=tg if rule == oracle.STRAIGHT else None)
+    dabs.dabs_problem_destroy(p)
+
+
+@pytest.mark.parametrize("rule", [oracle.MAXMIN, oracle.POSITIVEMIN, oracle.RANDOMMIN, oracle.CYCLICMIN,
+                                  oracle.TABU_GREEDY])
+def test_wide_search_parity_emptied_domains(rule):
+    """n <= tau: every bit becomes tabu and the rules fall back (R11)."""
+    W = inputs.wide_qubo(6, B31, 6)
+    p = load(W)
+    X0 = inputs.random_bits(4, 6, 6)
+    check_search(W, p, rule, X0, T=300, tau=16, trace_cap=400)
+    dabs.dabs_problem_destroy(p)
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("n,wt", [(4096, np.int16), (2048, np.int32)])
+def test_wide_search_parity_max_sizes(rule, n, wt):
+    """The largest dense problems (eight slots) on the wide kernels: int16
+    weights over the full range (B above 2^23), int32 W with B near 2^31."""
+    W = full16(n, n) if wt == np.int16 else inputs.wide_qubo(n, B31, n)
+    p = load(W)
+    assert dabs.dabs_problem_wide(p) == 1
+    X0 = inputs.random_bits(2, n, 7)
+    tg = inputs.random_bits(2, n, 8)
+    check_search(W, p, rule, X0, T=100, tau=0 if rule == oracle.TWONEIGHBOR else 8,
+                 targets=tg if rule == oracle.STRAIGHT else None)
+    dabs.dabs_problem_destroy(p)
+
+
+def test_wide_forced_equals_packed():
+    """One problem, the same calls on the packed-key and on the wide kernels:
+    identical outputs (and both the oracle's, by the tests above)."""
+    W = inputs.dense_qubo(800, -1000, 1000, 8)
+    p = load(W)
+    assert dabs.dabs_problem_wide(p) == 0
+    X0 = inputs.random_bits(8, 800, 1)
+    kw = dict(T=200, tau=8, seed=5, phase=1, inst0=0, targets=None, trace_cap=600)
+    for rule in (oracle.MAXMIN, oracle.POSITIVEMIN, oracle.RANDOMMIN, oracle.TABU_GREEDY):
+        a = gpu_search(p, rule, X0, **kw)
+        dabs.dabs_problem_set_wide(p, 1)
+        b = gpu_search(p, rule, X0, **kw)
+        dabs.dabs_problem_set_wide(p, 0)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (rule, k)
+    dabs.dabs_problem_destroy(p)
+
+
+@pytest.mark.parametrize("case", ["i32-200", "i16-300-full-range", "extreme-70"])
+def test_wide_batch_search_parity(case):
+    W, force = case_w(case)
+    n = W.shape[0]
+    p = load(W, force)
+    cnt = 10
+    X0 = inputs.random_bits(cnt, n, 1)
+    tg = inputs.random_bits(cnt, n, 2)
+    algos = np.array([oracle.MAIN_ALGOS[c % 5] for c in range(cnt)], np.int32)
+    ph0 = np.arange(cnt, dtype=np.uint32) * 7
+    T, Bn, tau, seed = max(2, n // 10), 3 * n, 8, 4242
+    x = to_dev(inputs.pack_bits(X0))
+    ph = to_dev(ph0)
+    best = torch.zeros_like(x)
+    be = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    e = torch.zeros(cnt, dtype=torch.int64, device=DEV)
+    fl = torch.zeros(cnt, dtype=torch.int32, device=DEV)
+    bp = dabs.dabs_batch_params(T=T, Bn=Bn, tau=tau, greedy_cap=CAP, seed=seed, inst0=11)
+    dabs.dabs_batch_search(p, bp, x, to_dev(inputs.pack_bits(tg)), to_dev(algos), ph, best, be, e, fl)
+    torch.cuda.synchronize()
+    gx = inputs.unpack_bits(x.cpu().numpy(), n)
+    gb = inputs.unpack_bits(best.cpu().numpy(), n)
+    for c in range(cnt):
+        r = oracle.batch_search(W, int(algos[c]), X0[c], tg[c], T=T, Bn=Bn, tau=tau, seed=seed, inst=11 + c,
+                                ph=int(ph0[c]), greedy_cap=CAP)
+        assert fl[c].item() == r["flips"] and ph[c].item() == r["ph"], c
+        assert e[c].item() == r["e"] and be[c].item() == r["ebest"], c
+        assert np.array_equal(gx[c], r["x"]) and np.array_equal(gb[c], r["best"]), c
+    dabs.dabs_problem_destroy(p)
+
+
+def test_wide_solver_parity_qap_large_penalty():
+    """A QAP QUBO of 20 facilities (n = 400 int32) with penalty p = 10^7:
+    delta bound far above the packed kernels' 2^26 - 2; device rounds
+    bit-exact with the oracle."""
+    F, D = inputs.qap_instance(20, 1)
+    W = inputs.qap_qubo(F, D, 10 ** 7)
+    n = W.shape[0]
+    assert dabs.dabs_fast_bound(dabs.DABS_W_I32, n) < oracle.delta_bound(W) <= B31
+    p = load(W)
+    assert dabs.dabs_problem_wide(p) == 1
+    kw = dict(T=40, Bn=400, tau=8, seed=4, capacity=8, npools=2, greedy_cap=CAP)
+    inst, rounds = 16, 3
+    s = dabs.dabs_solver_create(p, dabs.ga_params(**kw), inst)
+    dabs.dabs_solver_run(s, rounds)
+    nw = (n + 63) // 64
+    bits = torch.zeros((2, 8, nw), dtype=torch.int64, device=DEV)
+    pe = torch.zeros((2, 8), dtype=torch.int64, device=DEV)
+    x = torch.zeros((inst, nw), dtype=torch.int64, device=DEV)
+    e = torch.zeros(inst, dtype=torch.int64, device=DEV)
+    dabs.dabs_solver_pools(s, bits, pe)
+    dabs.dabs_solver_state(s, x, e)
+    torch.cuda.synchronize()
+    ref = oracle.solve(W, oracle.ga_params(**kw), inst, rounds)
+    assert np.array_equal(pe.cpu().numpy(), ref["pool_e"])
+    assert np.array_equal(inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), ref["pool_bits"])
+    assert np.array_equal(inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), ref["x"])
+    assert np.array_equal(e.cpu().numpy(), ref["e"])
+    dabs.dabs_solver_destroy(s)
+    dabs.dabs_problem_destroy(p)
+
+
+def test_wide_batched_mixed_graph_round():
+    """One graph-replayed batch of packed and wide problems (the wide ones in
+    classes of their own, flagged in the slot count): every problem evolves
+    exactly as the oracle runs it alone; the wide classes refuse the LDS
+    variant and run either register variant."""
+    problems = [inputs.dense_qubo(300, -100, 100, 1), inputs.wide_qubo(200, B31, 2),
+                full16(100, 3), inputs.wide_qubo(700, B31, 4),
+                inputs.dense_qubo(90, -100, 100, 5)]
+    kws = [dict(T=max(1, W.shape[0] // 10), Bn=W.shape[0], tau=8, seed=60 + k, capacity=5, npools=2)
+           for k, W in enumerate(problems)]
+    instances = [5, 6, 4, 3, 4]
+    rounds = 3
+    probs = [load(W) for W in problems]
+    assert [dabs.dabs_problem_wide(p) for p in probs] == [0, 1, 1, 1, 0]
+    b = dabs.dabs_batched_create(probs, [dabs.ga_params(greedy_cap=CAP, **kw) for kw in kws], instances)
+    classes = dabs.dabs_batched_classes(b)
+    wide = [c for c, cl in enumerate(classes) if cl[1] & 0x100]
+    assert len(wide) == 3
+    for c in wide:
+        with pytest.raises(dabs.DabsError):
+            dabs.dabs_batched_set_variant(b, c, 2)
+        dabs.dabs_batched_set_variant(b, c, c % 2)
+    dabs.dabs_batched_run(b, rounds, None, use_graph=True)
+    for q, W in enumerate(problems):
+        n = W.shape[0]
+        g = kws[q]
+        nw = (n + 63) // 64
+        bits = torch.zeros((g["npools"], g["capacity"], nw), dtype=torch.int64, device=DEV)
+        pe = torch.zeros((g["npools"], g["capacity"]), dtype=torch.int64, device=DEV)
+        x = torch.zeros((instances[q], nw), dtype=torch.int64, device=DEV)
+        ph = torch.zeros(instances[q], dtype=torch.int32, device=DEV)
+        dabs.dabs_batched_pools(b, q, bits, pe)
+        dabs.dabs_batched_state(b, q, x, None, ph)
+        torch.cuda.synchronize()
+        ref = oracle.solve(W, oracle.ga_params(greedy_cap=CAP, **kws[q]), instances[q], rounds)
+        assert np.array_equal(pe.cpu().numpy(), ref["pool_e"]), q
+        assert np.array_equal(inputs.unpack_bits(bits.cpu().numpy().view(np.uint64), n), ref["pool_bits"]), q
+        assert np.array_equal(inputs.unpack_bits(x.cpu().numpy().view(np.uint64), n), ref["x"]), q
+        assert np.array_equal(ph.cpu().numpy().view(np.uint32), ref["ph"]), q
+    dabs.dabs_batched_destroy(b)
+    for p in probs:
+        dabs.dabs_problem_destroy(p)
+
+
+def test_wide_bound_edges():
+    """B = 2^31 - 1 loads (wide kernels); 2^31 is refused; at the packed
+    bound the packed kernels serve, one above it the wide ones."""
+    for wt, n in ((np.int32, 200), (np.int16, 2048)):
+        wtype = dabs.DABS_W_I16 if wt == np.int16 else dabs.DABS_W_I32
+        fb = dabs.dabs_fast_bound(wtype, n)
+        for B, wide in ((fb, 0), (fb + 1, 1)):
+            W = np.zeros((n, n), np.int64)
+            if wt == np.int32:
+                W[0, 0] = B
+            else:
+                # row 0 reaches B through off-diagonal weights (the int16 diagonal is too small)
+                k, rem = divmod(B, 2 * 32767)
+                assert k + 1 <= n - 1
+                W[0, 1:k + 1] = W[1:k + 1, 0] = 32767
+                W[0, 0] = rem
+            p = load(W.astype(wt))
+            assert dabs.dabs_problem_info(p)[2] == B and dabs.dabs_problem_wide(p) == wide
+            dabs.dabs_problem_destroy(p)
+    W = np.zeros((5, 5), np.int64)
+    W[0, 0] = (1 << 31) - 1 - 2 * 3
+    W[0, 1] = W[1, 0] = 3
+    p = load(W.astype(np.int32))
+    assert dabs.dabs_problem_info(p)[2] == B31 and dabs.dabs_problem_wide(p) == 1
+    dabs.dabs_problem_destroy(p)
+    W[0, 0] += 1
+    with pytest.raises(dabs.DabsError) as e:
+        load(W.astype(np.int32))
+    assert e.value.status == dabs.DABS_E_RANGE
