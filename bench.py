@@ -431,6 +431,61 @@ def _timed_rounds(dabs, s, rounds, dev):
     return wall, int(tot.item()) - f0, walk_ms, launches
 
 
+def wide_kernels(dev, packed_flips_per_s, rounds=12):
+    """The wide-delta kernels (deltas as plain int32 words; dense W whose
+    delta bound exceeds the packed key words).  (a) the max-cut workload of
+    the headline line forced onto them (same rounds, same results: the cost
+    of the representation); (b) a QAP QUBO of Table III's shape, 20
+    facilities (n = 400 int32) with penalty p = 10^7, delta bound ~10^9, far
+    above the packed kernels' 2^26 - 2: 4096 instances, 8 pools x 100,
+    T = 0.1 n, Bn = 10 n, flips/s and the best assignment found."""
+    import torch
+    import paper_2207_03069_amd as dabs
+    out = {}
+    W, T, Bn = workload()
+    prob = dabs.dabs_problem_create(torch.from_numpy(W).to(dev))
+    dabs.dabs_problem_set_wide(prob, 1)
+    g = dabs.ga_params(T=T, Bn=Bn, tau=TAU, seed=SEED, capacity=CAPACITY, npools=NPOOLS,
+                       flags=dabs.DABS_SOLVER_TIME_WALK)
+    s = dabs.dabs_solver_create(prob, g, INSTANCES)
+    dabs.dabs_solver_run(s, 1)
+    wall, flips, walk_ms, launches = _timed_rounds(dabs, s, rounds, dev)
+    out["maxcut800_forced_wide"] = {"flips_per_s": flips / wall, "rounds": rounds,
+                                    "kernel_ms_per_launch": walk_ms / max(launches, 1),
+                                    "packed_flips_per_s": packed_flips_per_s,
+                                    "wide_over_packed": flips / wall / packed_flips_per_s}
+    del s
+    F, D = inputs.qap_instance(20, 0)
+    p = 10 ** 7
+    Wq = inputs.qap_qubo(F, D, p)
+    n = Wq.shape[0]
+    probq = dabs.dabs_problem_create(torch.from_numpy(Wq).to(dev))
+    bound = dabs.dabs_problem_info(probq)[2]
+    gq = dabs.ga_params(T=round(0.1 * n), Bn=10 * n, tau=TAU, seed=0, capacity=100, npools=8,
+                        flags=dabs.DABS_SOLVER_TIME_WALK)
+    sq = dabs.dabs_solver_create(probq, gq, 4096)
+    dabs.dabs_solver_run(sq, 1)
+    wall, flips, walk_ms, launches = _timed_rounds(dabs, sq, 6, dev)
+    nw = (n + 63) // 64
+    bits = torch.zeros((8, 100, nw), dtype=torch.int64, device=dev)
+    pe = torch.zeros((8, 100), dtype=torch.int64, device=dev)
+    dabs.dabs_solver_pools(sq, bits, pe)
+    torch.cuda.synchronize()
+    pe_h = pe.cpu().numpy()
+    q = int(np.argmin(pe_h[:, 0]))
+    x = inputs.unpack_bits(bits[q, 0:1].cpu().numpy().view(np.uint64), n)[0].reshape(20, 20)
+    feasible = bool((x.sum(axis=0) == 1).all() and (x.sum(axis=1) == 1).all())
+    cost = inputs.qap_cost(F, D, [int(np.argmax(x[i])) for i in range(20)]) if feasible else None
+    out["qap20_p1e7"] = {"workload": "QAP 20 facilities, flows/distances U[0,99], one-hot QUBO n=400 int32, "
+                                     "p=1e7; 4096 instances, 8 pools x 100, T=40, Bn=4000, tau=8",
+                         "delta_bound": int(bound), "packed_bound": dabs.dabs_fast_bound(dabs.DABS_W_I32, n),
+                         "wide": dabs.dabs_problem_wide(probq), "rounds": 6, "flips_per_s": flips / wall,
+                         "kernel_ms_per_launch": walk_ms / max(launches, 1), "best_energy": int(pe_h[q, 0]),
+                         "best_is_assignment": feasible, "assignment_cost": cost,
+                         "energy_check": (int(pe_h[q, 0]) == cost - 20 * p) if feasible else None}
+    return out
+
+
 def sparse_workloads(dev, lds_peak):
     """The sparse search kernel (deltas in LDS, a flip touching only the
     nonzeros of its row) on the sparse families of Section VI: a G22-like
@@ -600,6 +655,7 @@ def main():
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-rules", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 256 MiB device copy")
     ap.add_argument("--rule-costs", action="store_true", help="only time each search rule alone")
     args = ap.parse_args()
@@ -746,6 +802,10 @@ def main():
     if not args.no_tsp:
         print("bench: TSP ...", file=sys.stderr, flush=True)
         tsp = tsp_quality(dev)
+    wide = None
+    if not args.no_wide:
+        print("bench: wide-delta kernels ...", file=sys.stderr, flush=True)
+        wide = wide_kernels(dev, flips / dt)
     batched = None
     if not args.no_batched:
         print("bench: batched vs one problem at a time ...", file=sys.stderr, flush=True)
@@ -771,6 +831,7 @@ def main():
         "time_to_target_learned_vs_plain": learned,
         "time_to_target_batched_vs_single": batched,
         "tsp": tsp,
+        "wide_kernels": wide,
         "rule_costs": rules,
         "sparse": sparse,
         "small_n_lds_rows": small,
