@@ -318,3 +318,77 @@ def test_wide_bound_edges():
     with pytest.raises(dabs.DabsError) as e:
         load(W.astype(np.int32))
     assert e.value.status == dabs.DABS_E_RANGE
+
+
+def test_wide_time_to_target_and_checkpoint():
+    """The wide kernels record a reachable target as hit (and an unreachable
+    one as not), and a batch holding a wide problem checkpoints and restores
+    into later rounds identical to the uninterrupted ones."""
+    W = inputs.wide_qubo(150, B31, 11)
+    p = load(W)
+    assert dabs.dabs_problem_wide(p) == 1
+    g = dabs.ga_params(T=15, Bn=300, tau=8, seed=3, capacity=6, npools=2, greedy_cap=CAP)
+    s = dabs.dabs_solver_create(p, g, 24)
+    out = torch.zeros(2, dtype=torch.int64, device=DEV)
+    top = torch.tensor([1 << 62], dtype=torch.int64, device=DEV)         # reached at the first state
+    dabs.dabs_solver_run(s, 2, top)
+    dabs.dabs_solver_progress(s, out)
+    torch.cuda.synchronize()
+    assert out[0].item() >= 0
+    ref = oracle.solve(W, oracle.ga_params(T=15, Bn=300, tau=8, seed=3, capacity=6, npools=2, greedy_cap=CAP), 24, 2)
+    assert out[1].item() == ref["pool_e"].min()
+    dabs.dabs_solver_run(s, 1, torch.tensor([-(1 << 62)], dtype=torch.int64, device=DEV))
+    dabs.dabs_solver_progress(s, out)
+    torch.cuda.synchronize()
+    assert out[0].item() == -1
+    dabs.dabs_solver_destroy(s)
+
+    Ws = [W, inputs.dense_qubo(90, -60, 60, 1)]
+    params = [dabs.ga_params(T=15, Bn=150, seed=5, capacity=5, npools=2, greedy_cap=CAP),
+              dabs.ga_params(T=9, Bn=90, seed=6, capacity=5, npools=1, greedy_cap=CAP)]
+    inst = [10, 8]
+    probs = [p, load(Ws[1])]
+    a = dabs.dabs_batched_create(probs, params, inst)
+    dabs.dabs_batched_run(a, 2, None, use_graph=True)
+    blob = torch.zeros(dabs.dabs_batched_checkpoint(a), dtype=torch.uint8, device=DEV)
+    dabs.dabs_batched_checkpoint(a, blob)
+    dabs.dabs_batched_run(a, 3, None, use_graph=True)
+    b = dabs.dabs_batched_create(probs, params, inst)
+    dabs.dabs_batched_restore(b, blob)
+    dabs.dabs_batched_run(b, 3, None, use_graph=True)
+    for q, Wq in enumerate(Ws):
+        n = Wq.shape[0]
+        nw = (n + 63) // 64
+        got = []
+        for bb in (a, b):
+            bits = torch.zeros((params[q].npools, params[q].capacity, nw), dtype=torch.int64, device=DEV)
+            pe = torch.zeros((params[q].npools, params[q].capacity), dtype=torch.int64, device=DEV)
+            x = torch.zeros((inst[q], nw), dtype=torch.int64, device=DEV)
+            dabs.dabs_batched_pools(bb, q, bits, pe)
+            dabs.dabs_batched_state(bb, q, x)
+            torch.cuda.synchronize()
+            got.append((bits.cpu().numpy(), pe.cpu().numpy(), x.cpu().numpy()))
+        for u, v in zip(*got):
+            assert np.array_equal(u, v), q
+        ref = oracle.solve(Wq, oracle.ga_params(greedy_cap=CAP, T=params[q].T, Bn=params[q].Bn, seed=params[q].seed,
+                                                capacity=params[q].capacity, npools=params[q].npools), inst[q], 5)
+        assert np.array_equal(got[0][1], ref["pool_e"]), q
+    dabs.dabs_batched_destroy(a)
+    dabs.dabs_batched_destroy(b)
+    for pr in probs:
+        dabs.dabs_problem_destroy(pr)
+
+
+def test_wide_set_errors():
+    W = inputs.dense_qubo(40, -5, 5, 1)
+    p = load(W)
+    with pytest.raises(dabs.DabsError) as e:
+        dabs.dabs_problem_set_wide(p, 2)
+    assert e.value.status == dabs.DABS_E_INVALID
+    dabs.dabs_problem_destroy(p)
+    sp = dabs.dabs_problem_create_csr(*[to_dev(a) for a in inputs.csr_from_dense(W)], 40)
+    assert dabs.dabs_problem_wide(sp) == 0
+    with pytest.raises(dabs.DabsError) as e:
+        dabs.dabs_problem_set_wide(sp, 1)
+    assert e.value.status == dabs.DABS_E_UNSUPPORTED
+    dabs.dabs_problem_destroy(sp)
