@@ -431,6 +431,41 @@ def _timed_rounds(dabs, s, rounds, dev):
     return wall, int(tot.item()) - f0, walk_ms, launches
 
 
+RULE_OF = {2: "MaxMin", 3: "CyclicMin", 4: "RandomMin", 5: "PositiveMin", 6: "TwoNeighbor", 7: "TabuGreedy"}
+
+
+def round_tail(dabs, solver, dev):
+    """One more round of the timed solver with the per-item trace
+    (dabs_solver_trace_items): when each batch search ended, relative to its
+    launch, per main rule; the round lasts as long as its slowest item, and
+    the mean end over the launch is the share of the wave slots kept busy."""
+    import torch
+    nitems = dabs.dabs_solver_trace_items(solver)
+    buf = torch.zeros(4 * nitems, dtype=torch.int64, device=dev)
+    dabs.dabs_solver_trace_items(solver, buf)
+    dabs.dabs_solver_run(solver, 1)
+    dabs.dabs_solver_trace_items(solver, None)
+    torch.cuda.synchronize()
+    r = buf.view(nitems, 4).cpu().numpy().view(np.uint64).astype(np.int64)
+    end_us = (r[:, 1] - r[:, 0].min()) / 100.0
+    launch = float(end_us.max())
+    rule = (r[:, 3] >> 32) & 0xFF
+    flips = r[:, 3] & 0xFFFFFFFF
+    hw, xcc = r[:, 2] & 0xFFFFFFFF, r[:, 2] >> 32
+    simd = xcc * 4096 + ((hw >> 13) & 7) * 256 + ((hw >> 8) & 15) * 4 + ((hw >> 4) & 3)
+    per = {}
+    for k in sorted(set(rule.tolist())):
+        m = rule == k
+        per[RULE_OF.get(k, str(k))] = {"items": int(m.sum()), "flips_mean": float(flips[m].mean()),
+                                        "end_mean_us": float(end_us[m].mean()), "end_max_us": float(end_us[m].max())}
+    _, waves = np.unique(simd, return_counts=True)
+    return {"items": int(nitems), "launch_us": launch, "mean_end_over_launch": float(end_us.mean()) / launch,
+            "last_item_rule": RULE_OF.get(int(rule[np.argmax(end_us)])), "simds": int(len(waves)),
+            "items_per_simd_max": int(waves.max()), "per_rule": per,
+            "note": "one extra round after the timed steps, traced per item (start = the launch of the "
+                    "item's size class; every item is resident from the start here)"}
+
+
 def wide_kernels(dev, packed_flips_per_s, rounds=12):
     """The wide-delta kernels (deltas as plain int32 words; dense W whose
     delta bound exceeds the packed key words).  (a) the max-cut workload of
@@ -714,6 +749,7 @@ def main():
                                for k, v in algo_names.items()},
                 "record_found_by": {"operation": op_names[st[48]] if 0 <= st[48] < 8 else int(st[48]),
                                     "algorithm": algo_names.get(int(st[49]), int(st[49]))}}
+    tail = round_tail(dabs, solver, dev)
     del solver
 
     # roofline of the batch-search kernel.  Algorithmic bytes per flip: one
@@ -832,6 +868,7 @@ def main():
         "time_to_target_batched_vs_single": batched,
         "tsp": tsp,
         "wide_kernels": wide,
+        "round_tail": tail,
         "rule_costs": rules,
         "sparse": sparse,
         "small_n_lds_rows": small,

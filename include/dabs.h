@@ -353,6 +353,26 @@ int dabs_solver_set_cancel(dabs_solver *s, const volatile int32_t *flag_host);
 int dabs_solver_timing(dabs_solver *s, double *out_host, int32_t reset);
 
 /*
+ * Per-item trace of the batch searches of later rounds (Section III-B's batch
+ * search per instance; tracing, to see what sets a round's length).  Every
+ * round overwrites buf_dev (caller-owned device memory of at least 4 x items
+ * uint64 words) with one record per item of the round, at the item's
+ * position in the round's launch order (size classes in turn, each problem's
+ * items in the order its rules were sorted that round):
+ *   [0] the launch of the item's size class, [1] the item's end, in ticks
+ *       of the device's 100 MHz clock (items beyond the resident waves of
+ *       a launch start later than [0]);
+ *   [2] the wave's hardware ids: HW_ID register (bits 4-5 SIMD, 8-11 CU,
+ *       13-15 shader engine) | XCC_ID << 32;
+ *   [3] flips | main rule << 32 | problem << 40.
+ * Padding items of the LDS variant leave their record untouched.  buf_dev
+ * NULL stops tracing.  *items (nullable) receives the round's item count.
+ * Records cost one store per item; a captured round is captured again.
+ * Errors: DABS_E_INVALID (null handle, buffer shorter than 4 x items).
+ */
+int dabs_solver_trace_items(dabs_solver *s, uint64_t *buf_dev, int64_t words, int64_t *items);
+
+/*
  * Batched solver: many problems of uneven n served by one device loop.  Every
  * round draws the targets of all instances of all problems, runs their batch
  * searches (one wavefront per instance, one launch per weight type and slot
@@ -441,6 +461,8 @@ int dabs_batched_autotune(dabs_batched *b, double *ms_out, int32_t *choice_out, 
 int dabs_batched_set_variant(dabs_batched *b, int32_t cls, int32_t variant);
 int dabs_solver_autotune(dabs_solver *s, double *ms_out, int32_t *choice_out, void *stream);
 int dabs_batched_classes(const dabs_batched *b, int32_t *wtype_slots_count_variant, int32_t cap);
+/* As dabs_solver_trace_items, for a batch. */
+int dabs_batched_trace_items(dabs_batched *b, uint64_t *buf_dev, int64_t words, int64_t *items);
 
 /*
  * Ising front-end (Section I, Eq. (1)): H(S) = sum_{(i,j) in E} J_ij s_i s_j

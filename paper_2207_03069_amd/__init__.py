@@ -92,6 +92,8 @@ _SIGS = {
     "dabs_solver_state": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "dabs_solver_progress": ([_P, _P, _P], C.c_int),
     "dabs_solver_timing": ([_P, C.POINTER(C.c_double), C.c_int32], C.c_int),
+    "dabs_solver_trace_items": ([_P, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+    "dabs_batched_trace_items": ([_P, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "dabs_batched_create": ([_P, C.c_int32, _P, _P, _P, C.POINTER(_P)], C.c_int),
     "dabs_batched_destroy": ([_P], C.c_int),
     "dabs_batched_run": ([_P, C.c_int32, _P, C.c_int32, _P], C.c_int),
@@ -367,6 +369,18 @@ def dabs_solver_timing(s: Solver, reset: bool = False):
     return out[0], int(out[1]), int(out[2])
 
 
+def _trace_items(fn, handle, buf):
+    n = C.c_int64(0)
+    _check(fn(handle, _ptr(buf), 0 if buf is None else buf.numel(), C.byref(n)))
+    return n.value
+
+
+def dabs_solver_trace_items(s: Solver, buf=None) -> int:
+    """Per-item trace of later rounds into `buf` (int64 device tensor of at
+    least 4 x items words; None stops tracing).  Returns the item count."""
+    return _trace_items(lib().dabs_solver_trace_items, s.handle, buf)
+
+
 class Batched:
     def __init__(self, handle, problems, params, instances):
         self.handle, self.problems, self.params, self.instances = handle, problems, params, instances
@@ -535,6 +549,10 @@ def dabs_batched_set_mlp(b: Batched, m):
 
 
 # ------------------------------------------------------------------ autotuner
+def dabs_batched_trace_items(b: Batched, buf=None) -> int:
+    return _trace_items(lib().dabs_batched_trace_items, b.handle, buf)
+
+
 def dabs_batched_classes(b: Batched):
     """[(wtype, slots, items, variant)] of the batch's size classes."""
     nc = lib().dabs_batched_classes(b.handle, None, 0)

@@ -215,6 +215,15 @@ __global__ __launch_bounds__(256) void k_ga_target(BatchDev b, int total) {
 
 // Cost rank of a search rule (measured per flip: MaxMin, PositiveMin,
 // RandomMin, CyclicMin, tabu greedy, TwoNeighbor, then the rest).
+// The launch stamp of a size class in the per-item trace (record_item): word
+// 0 of each of its items' records, one clock read for all of them.
+__global__ __launch_bounds__(64) void k_trace_start(unsigned long long *trace, int base, int count) {
+    const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+    const unsigned long long t0 = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32)) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t);
+    for (int k = (int)threadIdx.x; k < count; k += (int)blockDim.x) trace[4 * ((int64_t)base + k)] = t0;
+}
+
 __device__ __forceinline__ int rule_rank(int a) {
     switch (a) {
     case MAXMIN: return 0;
@@ -607,6 +616,7 @@ struct dabs_batched {
     const volatile int32_t *cancel_host;  // the caller's pinned cancel flag (nullable)
     // optional timing of the batch-search kernels (DABS_SOLVER_TIME_WALK)
     bool timed;
+    unsigned long long *item_trace;    // nullable: the caller's per-item trace of each round
     static constexpr int NEV = 256;
     hipEvent_t ev[2 * NEV];
     int nev;
@@ -838,6 +848,12 @@ static int enqueue_round(dabs_batched *s, hipStream_t st, int ttt, bool capturin
         a.nitems = s->classes[c].count;
         a.ttt = ttt;
         a.lds_bytes = s->classes[c].lds_bytes;
+        a.trace = s->item_trace;
+        a.trace_base = s->classes[c].begin;
+        if (a.trace) {
+            hipLaunchKernelGGL(k_trace_start, dim3(1), dim3(WAVE), 0, cs, a.trace, a.trace_base, a.nitems);
+            HIP_OK(hipGetLastError());
+        }
         HIP_OK(launch_walk_items(s->classes[c].wtype, s->classes[c].slots, s->classes[c].variant, a, cs));
         if (nc > 1) HIP_OK(hipEventRecord(s->join[c], cs));
     }
@@ -1071,6 +1087,8 @@ int dabs_batched_autotune(dabs_batched *s, double *ms_out, int32_t *choice_out, 
                 a.nitems = s->classes[c].count;
                 a.ttt = 0;
                 a.lds_bytes = s->classes[c].lds_bytes;
+                a.trace = nullptr;
+                a.trace_base = 0;
                 if (status == DABS_OK &&
                     (hipEventRecord(e0, st) != hipSuccess ||
                      launch_walk_items(s->classes[c].wtype, s->classes[c].slots, v, a, st) != hipSuccess ||
@@ -1239,6 +1257,22 @@ int dabs_batched_classes(const dabs_batched *s, int32_t *wtype_slots_count_varia
     return nc;
 }
 
+int dabs_batched_trace_items(dabs_batched *s, uint64_t *buf_dev, int64_t words, int64_t *items) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
+    const int64_t n = s->classes.empty() ? 0 : (int64_t)s->classes.back().begin + s->classes.back().count;
+    if (items) *items = n;
+    if (buf_dev && words < 4 * n)
+        return dabs_fail(DABS_E_INVALID, "item trace of %lld words, the round has %lld items (4 words each)",
+                         (long long)words, (long long)n);
+    s->item_trace = (unsigned long long *)buf_dev;
+    if (s->graph_ready) {            // the captured round has the old kernel arguments
+        (void)hipGraphExecDestroy(s->exec);
+        (void)hipGraphDestroy(s->graph);
+        s->graph_ready = false;
+    }
+    return DABS_OK;
+}
+
 int dabs_batched_set_mlp(dabs_batched *s, const dabs_mlp *m) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null batch");
     if (m && !s->mlp_logits) {
@@ -1290,6 +1324,11 @@ int dabs_solver_create(const dabs_problem *p, const dabs_ga_params *g, int32_t i
 int dabs_solver_set_mlp(dabs_solver *s, const dabs_mlp *m) {
     if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
     return dabs_batched_set_mlp(s->b, m);
+}
+
+int dabs_solver_trace_items(dabs_solver *s, uint64_t *buf_dev, int64_t words, int64_t *items) {
+    if (!s) return dabs_fail(DABS_E_INVALID, "null solver");
+    return dabs_batched_trace_items(s->b, buf_dev, words, items);
 }
 
 int dabs_solver_autotune(dabs_solver *s, double *ms_out, int32_t *choice_out, void *stream) {

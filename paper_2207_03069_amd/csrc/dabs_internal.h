@@ -127,7 +127,27 @@ struct ItemsArgs {
     int32_t nitems;
     int32_t ttt;                   // record time to target
     int32_t lds_bytes;             // variant 2: LDS for the largest W of the class
+    int32_t trace_base;            // position of the class's first item in the round's item list
+    unsigned long long *trace;     // nullable: four words per item of the round (record_item)
 };
+
+// The per-item trace of a round (dabs_batched_trace_items): at the item's
+// position, the ticks of the 100 MHz device clock when its size class was
+// launched (written by k_trace_start: a start stamp written by the item itself
+// costs the search kernels ten registers) and when it ended, the wave's
+// hardware ids (HW_ID register, XCC_ID << 32) and flips | rule << 32 |
+// problem << 40.  Written by lane 0 after the batch search.
+__device__ __forceinline__ void record_item(const ItemsArgs &a, int idx, int flips, int rule, int prob) {
+    if (!a.trace) return;
+    const unsigned long long t_end = __builtin_amdgcn_s_memrealtime();
+    const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);
+    const unsigned xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);
+    unsigned long long *r = a.trace + 4 * ((int64_t)a.trace_base + idx);
+    r[1] = t_end;
+    r[2] = (unsigned long long)hw | ((unsigned long long)xcc << 32);
+    r[3] = (unsigned long long)(unsigned)flips | ((unsigned long long)(rule & 0xFF) << 32) |
+           ((unsigned long long)(unsigned)prob << 40);
+}
 // Compiled variants of the item kernel per (weight type, slot count): 0 caps a
 // wave at 128 VGPRs (4 waves per SIMD), 1 leaves the register file uncapped,
 // 2 (problems of one slot whose W fits, see lds_w_bytes) stages W in LDS,

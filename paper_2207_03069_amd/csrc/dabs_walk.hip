@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_walk_lds(WalkArgs a) {
 // for 2.
 template <int SLOTS> constexpr int CAPPED_WPE = SLOTS >= 8 ? 2 : 4;
 template <typename WT, int SLOTS, bool LDSW>
-__device__ __forceinline__ void walk_item(const ItemsArgs &a, int2 item, lds_ptr<const WT> Wl) {
+__device__ __forceinline__ void walk_item(const ItemsArgs &a, int2 item, int idx, lds_ptr<const WT> Wl) {
     typedef typename Walker<WT, SLOTS, LDSW>::vecH vecH;
     vecH kb0, kb1, mul0, mul1;
     const int lane = lane_id();
@@ -141,6 +141,7 @@ __device__ __forceinline__ void walk_item(const ItemsArgs &a, int2 item, lds_ptr
         b.e[gi] = w.E;
         b.best_e[gi] = w.Eb;
         atomicAdd(&b.ctr[0], (unsigned long long)f);
+        record_item(a, idx, f, b.algo[gi], p);
     }
 }
 
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     if (a.b.ctr[3]) return;               // the round is cancelled (latched before the launch)
     const int2 item = a.items[blockIdx.x];
     if (item.y < 0) return;               // padding of a class laid out for the LDS variant
-    walk_item<WT, SLOTS, false>(a, item, nullptr);
+    walk_item<WT, SLOTS, false>(a, item, (int)blockIdx.x, nullptr);
 }
 
 // Variant 2: four items of one problem per workgroup (the class's items are
@@ -163,9 +164,10 @@ __global__ __launch_bounds__(256) void k_walk_items_lds(ItemsArgs a) {
     const int p = a.items[4 * blockIdx.x].x;          // the first item of a group is never a dummy
     const ProbDesc *d = a.b.desc + p;
     stage_w<WT>((const WT *)d->W, d->ld, d->n, Wl, lds_row<WT>(d->n));
-    const int2 item = a.items[4 * blockIdx.x + (threadIdx.x >> 6)];
+    const int idx = 4 * (int)blockIdx.x + (int)(threadIdx.x >> 6);
+    const int2 item = a.items[idx];
     if (item.y < 0) return;
-    walk_item<WT, 1, true>(a, item, Wl);
+    walk_item<WT, 1, true>(a, item, idx, Wl);
 }
 
 template <typename WT, int SLOTS>

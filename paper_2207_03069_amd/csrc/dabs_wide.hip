@@ -88,6 +88,7 @@ __global__ __launch_bounds__(64) void k_walk_items_wide(ItemsArgs a) {
         b.e[gi] = w.E;
         b.best_e[gi] = w.Eb;
         atomicAdd(&b.ctr[0], (unsigned long long)f);
+        record_item(a, (int)blockIdx.x, f, b.algo[gi], p);
     }
 }
 

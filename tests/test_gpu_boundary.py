@@ -420,3 +420,61 @@ def test_checkpoint_shape_mismatch_and_size():
             dabs.dabs_solver_restore(c, blob)
     with pytest.raises(dabs.DabsError):
         dabs.dabs_solver_restore(a, torch.zeros(nbytes, dtype=torch.uint8, device=DEV))   # no header
+
+
+def test_item_trace_of_a_round():
+    """The per-item trace of a round: one record per item of the packed,
+    wide-delta and sparse kernels, with the class's launch stamp before the
+    item's end, its problem, main rule and flips (summing to the round's
+    flips), the wave's SIMD ids; tracing changes no result and stops when
+    switched off."""
+    Ws = [inputs.dense_qubo(300, -60, 60, 1), inputs.wide_qubo(200, (1 << 31) - 1, 2),
+          inputs.maxcut_instance(500, 0.02, seed=3)[0]]
+    mk = [lambda W: dabs.dabs_problem_create(dev(W))] * 2 + \
+         [lambda W: dabs.dabs_problem_create_csr(*[dev(a) for a in inputs.csr_from_dense(W)], W.shape[0])]
+    params = [dabs.ga_params(T=W.shape[0] // 10, Bn=W.shape[0], seed=7 + k, capacity=5, npools=2, greedy_cap=100000)
+              for k, W in enumerate(Ws)]
+    inst = [9, 6, 5]
+    probs = [f(W) for f, W in zip(mk, Ws)]
+    a = dabs.dabs_batched_create(probs, params, inst)
+    b = dabs.dabs_batched_create(probs, params, inst)
+    items = dabs.dabs_batched_trace_items(a)
+    assert items == sum(inst)
+    buf = torch.zeros(4 * items, dtype=torch.int64, device=DEV)
+    with pytest.raises(dabs.DabsError):
+        dabs.dabs_batched_trace_items(a, buf[:-1])
+    dabs.dabs_batched_trace_items(a, buf)
+    tot = torch.zeros(1, dtype=torch.int64, device=DEV)
+    dabs.dabs_batched_run(a, 1, None, use_graph=True)
+    dabs.dabs_batched_flips(a, tot)
+    f1 = int(tot.item())
+    dabs.dabs_batched_run(a, 1, None, use_graph=True)
+    dabs.dabs_batched_flips(a, tot)
+    torch.cuda.synchronize()
+    r = buf.view(items, 4).cpu().numpy().view(np.uint64).astype(np.int64)
+    start, end, hw, w3 = r[:, 0], r[:, 1], r[:, 2], r[:, 3]
+    assert np.all(start > 0) and np.all(end >= start)
+    flips, rule, prob = w3 & 0xFFFFFFFF, (w3 >> 32) & 0xFF, w3 >> 40
+    assert int(flips.sum()) == int(tot.item()) - f1
+    assert np.array_equal(np.bincount(prob, minlength=3), inst)
+    assert set(rule.tolist()) <= {dabs.DABS_MAXMIN, dabs.DABS_CYCLICMIN, dabs.DABS_RANDOMMIN, dabs.DABS_POSITIVEMIN,
+                                  dabs.DABS_TWONEIGHBOR}
+    assert np.all((hw >> 32) < 8) and np.all(((hw >> 4) & 3) < 4)
+    for c in np.unique(prob):                       # one launch stamp per size class (one class per problem here)
+        assert len(np.unique(start[prob == c])) == 1
+    dabs.dabs_batched_trace_items(a, None)
+    before = buf.clone()
+    dabs.dabs_batched_run(a, 1, None, use_graph=True)
+    dabs.dabs_batched_run(b, 3, None, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(buf, before)
+    for q, W in enumerate(Ws):
+        nw = (W.shape[0] + 63) // 64
+        got = []
+        for bb in (a, b):
+            pe = torch.zeros((2, 5), dtype=torch.int64, device=DEV)
+            bits = torch.zeros((2, 5, nw), dtype=torch.int64, device=DEV)
+            dabs.dabs_batched_pools(bb, q, bits, pe)
+            torch.cuda.synchronize()
+            got.append((pe.cpu().numpy(), bits.cpu().numpy()))
+        assert np.array_equal(got[0][0], got[1][0]) and np.array_equal(got[0][1], got[1][1]), q
