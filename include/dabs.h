@@ -365,7 +365,7 @@ int dabs_solver_timing(dabs_solver *s, double *out_host, int32_t reset);
  *   [2] the wave's hardware ids: HW_ID register (bits 4-5 SIMD, 8-11 CU,
  *       13-15 shader engine) | XCC_ID << 32;
  *   [3] flips | main rule << 32 | problem << 40.
- * Padding items of the LDS variant leave their record untouched.  buf_dev
+ * Padding items of the LDS variant get word [0] only.  buf_dev
  * NULL stops tracing.  *items (nullable) receives the round's item count.
  * Records cost one store per item; a captured round is captured again.
  * Errors: DABS_E_INVALID (null handle, buffer shorter than 4 x items).
