@@ -478,3 +478,33 @@ def test_item_trace_of_a_round():
             torch.cuda.synchronize()
             got.append((pe.cpu().numpy(), bits.cpu().numpy()))
         assert np.array_equal(got[0][0], got[1][0]) and np.array_equal(got[0][1], got[1][1]), q
+
+
+def test_item_trace_lds_variant():
+    """The LDS variant lays a class out in groups of four items of one
+    problem (dummies pad each problem): the real items are recorded once
+    each, the dummies get the launch stamp only."""
+    Ws = [inputs.dense_qubo(100, -60, 60, 4), inputs.dense_qubo(60, -60, 60, 5)]
+    params = [dabs.ga_params(T=10, Bn=100, seed=3, capacity=5, npools=1, greedy_cap=100000),
+              dabs.ga_params(T=6, Bn=60, seed=4, capacity=5, npools=1, greedy_cap=100000)]
+    inst = [6, 5]
+    probs = [dabs.dabs_problem_create(dev(W)) for W in Ws]
+    b = dabs.dabs_batched_create(probs, params, inst)
+    classes = dabs.dabs_batched_classes(b)
+    assert len(classes) == 1 and classes[0][3] == 2          # one class, W in LDS
+    items = dabs.dabs_batched_trace_items(b)
+    assert items == 8 + 8                                    # each problem padded to a multiple of four
+    buf = torch.zeros(4 * items, dtype=torch.int64, device=DEV)
+    dabs.dabs_batched_trace_items(b, buf)
+    tot = torch.zeros(1, dtype=torch.int64, device=DEV)
+    dabs.dabs_batched_run(b, 2, None, use_graph=True)
+    dabs.dabs_batched_flips(b, tot)
+    torch.cuda.synchronize()
+    r = buf.view(items, 4).cpu().numpy().view(np.uint64).astype(np.int64)
+    assert np.all(r[:, 0] > 0)
+    real = r[:, 1] > 0
+    assert int(real.sum()) == sum(inst)
+    assert np.all(r[~real, 2:] == 0)
+    prob = r[real, 3] >> 40
+    assert np.array_equal(np.bincount(prob, minlength=2), inst)
+    assert np.all(r[real, 1] >= r[real, 0])
