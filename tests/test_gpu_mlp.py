@@ -251,17 +251,22 @@ def exact_ga_network():
 
 
 @pytest.mark.parametrize("n,wt,ops", [(90, np.int16, tuple(range(10))), (70, np.int32, (8, 9, 2)),
-                                      (130, np.int16, (8, 9))])
+                                      (130, np.int16, (8, 9)), (70, "wide", (8, 9, 2))])
 def test_learned_ga_bit_exact_with_oracle(n, wt, ops):
     """The learned operations inside device rounds (pool scoring, parent
     logits, MLP-seed / MLP-mutate targets) against the oracle's generational
-    loop with the same network: pools, states and energies bit for bit."""
-    W = inputs.dense_qubo(n, -100, 100, 21 + n, dtype=wt)
+    loop with the same network: pools, states and energies bit for bit (also
+    on the wide-delta kernels, with a delta bound near 2^31)."""
+    if wt == "wide":
+        W = inputs.wide_qubo(n, (1 << 31) - 1, 21 + n)
+    else:
+        W = inputs.dense_qubo(n, -100, 100, 21 + n, dtype=wt)
     params = exact_ga_network()
     inst, P, m, rounds, seed = 16, 2, 8, 4, 5
     g = dabs.ga_params(T=max(1, n // 8), Bn=2 * n, tau=8, seed=seed, capacity=m, npools=P, ops=ops,
                        greedy_cap=100000)
     p = dabs.dabs_problem_create(dev(W))
+    assert dabs.dabs_problem_wide(p) == (wt == "wide")
     s = dabs.dabs_solver_create(p, g, inst)
     net = dabs.dabs_mlp_create(params)
     dabs.dabs_solver_set_mlp(s, net)
